@@ -1,0 +1,173 @@
+"""Benchmark of the MaxSS hot path on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic reads
+already resident in HBM: maxss_scan_reads (read encoding, the MaxSS scan of
+every read against every fragment on both strands, top-2 merge, exact re-scan
+of the two winners) followed by maxss_align_top (NW of every read on its best
+fragment).  The metric is MaxSS GCUPS = (sum over reads of 2 * G * m) / step
+time / 1e9 (both strands, every genome start position).
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build measures
+one GPU (see the sharding notes in the design document).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for the roofline objects
+HBM_PEAK_GBS = 8000.0
+CU, SIMD_LANES, CLOCK = 256, 64, 2.4e9          # 256 CUs x 4 SIMD16 = 64 lanes/clk/CU
+INT16_PACKED_OPS = CU * SIMD_LANES * CLOCK * 2   # 16-bit lane ops/s with packed math
+OPS_PER_CELL = 3   # substitution-score select, saturating add (Kadane's add+clamp), running max
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s: float = 15.0):
+    """The oracle as it stands on this host, on a bounded prefix of the
+    workload's reads (scan + NW), in GCUPS."""
+    import numpy as np
+
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    G = w.genome.G
+    lens = w.reads.lengths()
+    # calibrate on a few reads, then size the sample to the time budget
+    k0 = min(threads, w.reads.n)
+    sub = w.reads.subset(np.arange(k0))
+    t0 = time.perf_counter()
+    top = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, nthreads=threads)
+    oracle.align_top(w.genome.seq, w.F, sub.seq, sub.offsets, top, w.pad, w.M, w.X, w.gap)
+    dt0 = time.perf_counter() - t0
+    k = int(max(k0, min(w.reads.n, k0 * max(1.0, (budget_s - dt0) / max(dt0, 1e-3)))))
+    k = (k // threads) * threads or k0
+    sub = w.reads.subset(np.arange(k0, k0 + k) % w.reads.n)
+    t0 = time.perf_counter()
+    top = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, nthreads=threads)
+    oracle.align_top(w.genome.seq, w.F, sub.seq, sub.offsets, top, w.pad, w.M, w.X, w.gap)
+    dt = time.perf_counter() - t0
+    cells = 2.0 * G * float(sub.lengths().sum())
+    return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of the %d reads (scan both strands + top-2 + NW), %.1f s" % (
+                k, w.reads.n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bacterial",
+                    choices=["tiny", "bacterial", "chromosome", "damaged"])
+    ap.add_argument("--reads", type=int, default=None, help="override the read count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the MaxSS scan shards by reads with no "
+              "collective, and this build reports the single-GPU rate (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1403_2136_amd as mx
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    w = gen.workload(args.workload, n_reads=args.reads)
+    log("workload %s: G=%d reads=%d (%.1fs)" % (w.name, w.genome.G, w.reads.n, time.time() - t0))
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap)
+    n = w.reads.n
+    seq = torch.from_numpy(w.reads.seq).to(dev)
+    off = torch.from_numpy(w.reads.offsets.astype(np.int64)).to(dev)
+    top = torch.empty(n * 32, dtype=torch.uint8, device=dev)
+    aln = torch.empty(n * 32, dtype=torch.uint8, device=dev)
+    stride = 256
+    cig = torch.empty(n * stride, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    G = w.genome.G
+    cells = 2.0 * G * float(w.reads.lengths().sum())
+
+    def step():
+        ix.scan(seq, off, top, stream=stream)
+        ix.align(seq, off, top, w.pad, stride, aln, cig, stream=stream)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    mx.maxss_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    scan_ms, scan_k = mx.maxss_profile_read("scan")
+    nw_ms, nw_k = mx.maxss_profile_read("nw")
+    other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
+    mx.maxss_profile_enable(False)
+    log("timed %d steps in %.3fs; scan kernel %.3f ms/launch, nw %.3f ms/launch, %s" % (
+        args.steps, dt, scan_ms / max(scan_k, 1), nw_ms / max(nw_k, 1),
+        {k: round(v[0] / max(v[1], 1), 3) for k, v in other.items()}))
+    ms_step = dt / args.steps * 1e3
+    gcups = cells / (dt / args.steps) / 1e9
+    scan_s = scan_ms / max(scan_k, 1) / 1e3
+    achieved = OPS_PER_CELL * cells / scan_s / 1e12
+    peak = INT16_PACKED_OPS / 1e12
+    res = {
+        "metric": "MaxSS GCUPS; reads/s, learned-proposal vs full scan at >=99% top-1 agreement",
+        "value": round(gcups, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %d bp genome, F=%d (%d fragments), %d reads, lengths %d-%d, both "
+                        "strands, match %d mismatch %d gap %d; step = scan + top-2 + NW" % (
+                            w.name, G, w.F, ix.NF, n, int(w.reads.lengths().min()),
+                            int(w.reads.lengths().max()), w.M, w.X, w.gap),
+            "reads_per_s": round(n / (dt / args.steps), 1),
+            "scan_gcups_kernel": round(cells / scan_s / 1e9, 1),
+            "scan_ms_per_launch": round(scan_s * 1e3, 3),
+            "nw_ms_per_launch": round(nw_ms / max(nw_k, 1), 3),
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(peak, 2),
+            "unit": "Tops/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    ix.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

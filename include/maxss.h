@@ -1,0 +1,192 @@
+/*
+ * maxss.h -- C ABI of libmaxss, an MI355X (gfx950) implementation of the
+ * MaxSSmap hot path (Turki & Roshan, "MaxSSmap: A GPU program for mapping
+ * divergent short reads to genomes with the maximum scoring subsequence").
+ *
+ * The mapping problem, as the paper states it (Methods, "Overview", "First
+ * phase of MaxSSmap", "Second phase of MaxSSmap"): the genome is cut into
+ * disjoint fragments of a user-given length; every read is scored against
+ * every fragment with the maximum scoring subsequence of the ungapped
+ * substitution scores of a read-length window slid along the fragment; the
+ * best and second-best fragments are reported; the read is then aligned with
+ * Needleman-Wunsch to the genome region of the best fragment.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns a maxss_status; on failure maxss_last_error() gives a
+ *     thread-local message.  No C++ exception crosses this boundary.  On
+ *     failure the outputs are unspecified and the inputs are untouched.
+ *   - The caller owns every read, output and CIGAR buffer; the library owns
+ *     indexes and frees them only in maxss_index_free.  The library never
+ *     frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     With device-resident reads (maxss_reads.on_device = 1) every pointer
+ *     argument of the call must be device memory and the call is
+ *     asynchronous on `stream`; with host reads every pointer is host memory
+ *     and the call returns when the results are in the host buffers.
+ *   - Bases are ASCII A, C, G, T, N in either case.  N (in the genome, in a
+ *     read, or the padding past the genome end) scores `mismatch` against
+ *     everything, including N.
+ *   - All scores are exact integers.
+ */
+#ifndef MAXSS_H
+#define MAXSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MAXSS_OK = 0,
+  MAXSS_EINVAL = -1,   /* bad argument, bad character, bad parameter range   */
+  MAXSS_ENOMEM = -2,   /* host or device allocation failed                   */
+  MAXSS_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed         */
+  MAXSS_ETOOLONG = -4, /* a read is empty or longer than max_read_len        */
+  MAXSS_ESTATE = -5    /* the call does not fit the object's state           */
+} maxss_status;
+
+/* maxss_params.flags */
+#define MAXSS_ONE_STRAND 1u /* scan only the read as given (no reverse complement) */
+#define MAXSS_NW_GLOBAL 2u  /* end-to-end NW instead of fitting the whole read     */
+
+/* Scoring and fragmenting parameters, fixed when the genome is indexed.
+ *   match        M, score of two equal bases (not N); 1..127.
+ *   mismatch     X, score of any other pair; -127..0.
+ *   gap          linear gap score of the second phase (NW); -1000000..0.
+ *   frag_len     F, fragment length; > 0 and a multiple of 16 (Methods,
+ *                "Byte packing for faster global memory access").
+ *   max_read_len longest read any later call may pass; 1..8192 and
+ *                max_read_len * match <= 65535 (the scan's 16-bit exact range).
+ *   flags        MAXSS_ONE_STRAND, MAXSS_NW_GLOBAL. */
+typedef struct {
+  int32_t match;
+  int32_t mismatch;
+  int32_t gap;
+  uint32_t frag_len;
+  uint32_t max_read_len;
+  uint32_t flags;
+} maxss_params;
+
+typedef struct maxss_index maxss_index; /* opaque, immutable once built */
+
+/* A batch of reads of any lengths, concatenated (CSR): read i is
+ * seq[offsets[i], offsets[i+1]).  offsets has n+1 entries, offsets[0] may be
+ * non-zero.  on_device: 1 if seq and offsets are device pointers. */
+typedef struct {
+  const char* seq;
+  const uint64_t* offsets;
+  uint32_t n;
+  uint32_t on_device;
+} maxss_reads;
+
+/* Per-read result of the scan (32 bytes).  Entry 0 is the best fragment,
+ * entry 1 the best other fragment (-1 in every field when the genome has one
+ * fragment).  score: the fragment's value, the largest window score over both
+ * strands and every start offset o in [0, F) of the fragment.  strand (0 =
+ * read as given, 1 = reverse complement) and offset are those of the
+ * fragment's representative window: the smallest strand, then the smallest
+ * offset, among the windows reaching the value.  Ties between fragments go to
+ * the smaller fragment id.  For device-resident reads, a read that is empty,
+ * longer than max_read_len or holds a character other than ACGTN gets
+ * frag[0] = MAXSS_READ_INVALID and no other field is meaningful. */
+typedef struct {
+  int32_t frag[2];
+  int32_t score[2];
+  int32_t offset[2];
+  int8_t strand[2];
+  int8_t _pad[6];
+} maxss_top2;
+
+#define MAXSS_READ_INVALID (-2)
+
+/* Per-read result of the second phase (32 bytes).  score: the NW score;
+ * strand: orientation of the read that was aligned; [ref_begin, ref_end): the
+ * genome span the alignment covers (0-based, half-open); cigar_len: length of
+ * the run-length CIGAR string written for the read ('=' match, 'X' mismatch,
+ * 'I' read base against a gap, 'D' genome base against a gap).  flags bit 0:
+ * the CIGAR did not fit cigar_stride and was truncated; bit 1: the read was
+ * invalid, or its top[i] record named no valid fragment (frag[0] outside
+ * [0, NF) or strand[0] not 0/1), and was not aligned. */
+typedef struct {
+  int32_t score;
+  int8_t strand;
+  int8_t flags;
+  int8_t _pad[2];
+  int64_t ref_begin;
+  int64_t ref_end;
+  uint32_t cigar_len;
+  uint32_t _pad2;
+} maxss_aln;
+
+#define MAXSS_ALN_TRUNCATED 1
+#define MAXSS_ALN_SKIPPED 2
+
+/* Index a genome (Methods, "Overview"; "Coalescent global memory access";
+ * "Byte packing").  seq: host pointer to len ASCII bases.  The genome is cut
+ * into NF = ceil(len / F) fragments; positions past len are N.  The index is
+ * built on the current HIP device and holds the genome there 2-bit packed with
+ * an N mask.  Errors: EINVAL (len = 0, a bad character, a parameter out of the
+ * ranges above, NULL pointer), ENOMEM, EDEVICE.  *out is set only on success. */
+maxss_status maxss_index_genome(const char* seq, uint64_t len, const maxss_params* params,
+                                maxss_index** out);
+
+/* Free an index (NULL is a no-op).  Must not race with calls using it. */
+void maxss_index_free(maxss_index* index);
+
+/* Genome length, fragment count and fragment length of an index (any output
+ * pointer may be NULL).  Errors: EINVAL on a NULL index. */
+maxss_status maxss_index_info(const maxss_index* index, uint64_t* genome_len,
+                              uint32_t* num_fragments, uint32_t* frag_len);
+
+/* First phase (Methods, "First phase of MaxSSmap"; Figure 1): for every read,
+ * the maximum scoring subsequence score of every (strand, fragment, offset)
+ * window -- the window of read length m starting at genome position
+ * f*F + o may run into the next fragment and past the genome end -- reduced to
+ * the best and second-best fragments (one maxss_top2 per read, in read
+ * order).  Reads of any lengths may be mixed in one call.
+ * out: n records, host or device memory as the reads.
+ * Errors: EINVAL (NULL pointers, n = 0 is allowed and does nothing), ETOOLONG
+ * (host reads only: a read of length 0 or > max_read_len), ENOMEM, EDEVICE. */
+maxss_status maxss_scan_reads(const maxss_index* index, const maxss_reads* reads,
+                              maxss_top2* out, void* stream);
+
+/* Second phase (Methods, "Second phase of MaxSSmap"): for every read,
+ * Needleman-Wunsch with a linear gap of the read, in the orientation of
+ * top[i].strand[0], against the genome region
+ *   [max(0, f*F - pad), min(G, f*F + F + m - 1 + pad)),  f = top[i].frag[0],
+ * i.e. the scanned (extended) best fragment widened by pad bases each side.
+ * Fitting mode (default): the whole read against a free-ended stretch of the
+ * region; MAXSS_NW_GLOBAL: the read against the whole region.  Traceback
+ * prefers diagonal, then I, then D; in fitting mode the end column is the
+ * smallest one reaching the best score.
+ * top: n records from maxss_scan_reads; out: n records; cigar: n *
+ * cigar_stride bytes, read i's NUL-terminated CIGAR at cigar + i*cigar_stride
+ * (cigar_stride >= 2; a CIGAR that does not fit is truncated and flagged).
+ * Pointers are host or device memory as the reads.  Errors: EINVAL, ETOOLONG
+ * (host reads), ENOMEM, EDEVICE. */
+maxss_status maxss_align_top(const maxss_index* index, const maxss_reads* reads,
+                             const maxss_top2* top, uint32_t pad, maxss_aln* out,
+                             char* cigar, uint64_t cigar_stride, void* stream);
+
+/* Kernel timing for measurement.  maxss_profile_enable(1) clears the records
+ * and brackets every later launch of the library's kernels with HIP events on
+ * the launch stream; maxss_profile_enable(0) stops recording.
+ * maxss_profile_read waits for the recorded events of the kernel `name`
+ * ("encode", "scan", "merge", "rescan", "nw") and returns their summed
+ * duration in milliseconds and the number of launches.  Not for use while a
+ * stream is being captured into a graph.  Errors: EINVAL (NULL), EDEVICE. */
+maxss_status maxss_profile_enable(int on);
+maxss_status maxss_profile_read(const char* name, double* total_ms, uint32_t* launches);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* maxss_last_error(void);
+
+/* Library version string. */
+const char* maxss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAXSS_H */

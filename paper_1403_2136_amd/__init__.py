@@ -1,0 +1,264 @@
+"""Python binding of libmaxss (MaxSSmap hot path on MI355X / gfx950).
+
+Argument marshalling only: every step of the path runs in the HIP library
+(``csrc/``, C ABI in ``include/maxss.h``).  PyTorch is used for device memory
+and streams.  The functions keep the C names; ``Index`` is a small owner of
+the opaque index handle.  Importing this module does not need a GPU, but every
+call that computes fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmaxss.so")
+
+MAXSS_OK = 0
+MAXSS_EINVAL = -1
+MAXSS_ENOMEM = -2
+MAXSS_EDEVICE = -3
+MAXSS_ETOOLONG = -4
+MAXSS_ESTATE = -5
+MAXSS_ONE_STRAND = 1
+MAXSS_NW_GLOBAL = 2
+MAXSS_READ_INVALID = -2
+MAXSS_ALN_TRUNCATED = 1
+MAXSS_ALN_SKIPPED = 2
+
+TOP2_DTYPE = np.dtype([("frag", "<i4", (2,)), ("score", "<i4", (2,)),
+                       ("offset", "<i4", (2,)), ("strand", "i1", (2,)),
+                       ("pad", "i1", (6,))])
+ALN_DTYPE = np.dtype([("score", "<i4"), ("strand", "i1"), ("flags", "i1"), ("pad", "i1", (2,)),
+                      ("ref_begin", "<i8"), ("ref_end", "<i8"), ("cigar_len", "<u4"),
+                      ("pad2", "<u4")])
+assert TOP2_DTYPE.itemsize == 32 and ALN_DTYPE.itemsize == 32
+
+
+class MaxssError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("maxss status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap", ctypes.c_int32),
+                ("frag_len", ctypes.c_uint32), ("max_read_len", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Reads(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_uint32),
+                ("on_device", ctypes.c_uint32)]
+
+
+# every function declared in include/maxss.h
+EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_scan_reads",
+           "maxss_align_top", "maxss_profile_enable", "maxss_profile_read", "maxss_last_error",
+           "maxss_version")
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime with the same soname as the system
+        # one; loading torch first makes libmaxss bind to that copy, so that
+        # torch's device memory and streams and this library share a runtime.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmaxss.so is not built (run __graft_entry__.build() or "
+                               "python paper_1403_2136_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        c = ctypes
+        L.maxss_index_genome.restype = c.c_int
+        L.maxss_index_genome.argtypes = [c.c_void_p, c.c_uint64, c.POINTER(Params),
+                                         c.POINTER(c.c_void_p)]
+        L.maxss_index_free.restype = None
+        L.maxss_index_free.argtypes = [c.c_void_p]
+        L.maxss_index_info.restype = c.c_int
+        L.maxss_index_info.argtypes = [c.c_void_p, c.POINTER(c.c_uint64), c.POINTER(c.c_uint32),
+                                       c.POINTER(c.c_uint32)]
+        L.maxss_scan_reads.restype = c.c_int
+        L.maxss_scan_reads.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p, c.c_void_p]
+        L.maxss_align_top.restype = c.c_int
+        L.maxss_align_top.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p, c.c_uint32,
+                                      c.c_void_p, c.c_void_p, c.c_uint64, c.c_void_p]
+        L.maxss_profile_enable.restype = c.c_int
+        L.maxss_profile_enable.argtypes = [c.c_int]
+        L.maxss_profile_read.restype = c.c_int
+        L.maxss_profile_read.argtypes = [c.c_char_p, c.POINTER(c.c_double), c.POINTER(c.c_uint32)]
+        L.maxss_last_error.restype = c.c_char_p
+        L.maxss_last_error.argtypes = []
+        L.maxss_version.restype = c.c_char_p
+        L.maxss_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != MAXSS_OK:
+        raise MaxssError(st, lib().maxss_last_error().decode(errors="replace"))
+
+
+def _ptr(x):
+    """Data pointer of a numpy array, torch tensor, bytes or int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError(type(x))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _as_u8(seq) -> np.ndarray:
+    if isinstance(seq, (bytes, bytearray)):
+        return np.frombuffer(bytes(seq), dtype=np.uint8)
+    if isinstance(seq, str):
+        return np.frombuffer(seq.encode(), dtype=np.uint8)
+    return np.ascontiguousarray(seq, dtype=np.uint8)
+
+
+def maxss_version() -> str:
+    return lib().maxss_version().decode()
+
+
+def maxss_profile_enable(on: bool) -> None:
+    _check(lib().maxss_profile_enable(1 if on else 0))
+
+
+def maxss_profile_read(name: str):
+    """(total_ms, launches) of kernel `name` since profiling was enabled."""
+    t, k = ctypes.c_double(), ctypes.c_uint32()
+    _check(lib().maxss_profile_read(name.encode(), ctypes.byref(t), ctypes.byref(k)))
+    return t.value, k.value
+
+
+def maxss_index_genome(seq, frag_len: int, max_read_len: int, match: int = 1,
+                       mismatch: int = -1, gap: int = -2, flags: int = 0) -> int:
+    g = _as_u8(seq)
+    p = Params(match, mismatch, gap, frag_len, max_read_len, flags)
+    h = ctypes.c_void_p()
+    _check(lib().maxss_index_genome(g.ctypes.data, g.size, ctypes.byref(p), ctypes.byref(h)))
+    return h.value
+
+
+def maxss_index_free(handle: int) -> None:
+    lib().maxss_index_free(handle)
+
+
+def maxss_index_info(handle: int):
+    G, NF, F = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().maxss_index_info(handle, ctypes.byref(G), ctypes.byref(NF), ctypes.byref(F)))
+    return G.value, NF.value, F.value
+
+
+def _reads_struct(seq, offsets, on_device: bool) -> Reads:
+    n = (offsets.numel() if hasattr(offsets, "numel") else len(offsets)) - 1
+    return Reads(_ptr(seq), _ptr(offsets), n, 1 if on_device else 0)
+
+
+def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None):
+    """Top-2 records for a batch of reads.
+
+    Host form: seq (bytes / uint8 array), offsets (uint64 array, n+1) ->
+    returns a numpy array of TOP2_DTYPE.  Device form: seq and offsets are
+    torch device tensors (uint8, int64 holding the offsets) and `out` a torch
+    device tensor of n*32 bytes; the call is asynchronous on `stream`."""
+    if hasattr(seq, "is_cuda") and seq.is_cuda:
+        r = _reads_struct(seq, offsets, True)
+        if out is None:
+            raise ValueError("device reads need a device `out` tensor of n*32 bytes")
+        _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), _ptr(out),
+                                      _stream_handle(stream)))
+        return out
+    s = _as_u8(seq)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = off.size - 1
+    res = np.zeros(n, dtype=TOP2_DTYPE) if out is None else out
+    r = Reads(s.ctypes.data, off.ctypes.data, n, 0)
+    _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), res.ctypes.data,
+                                  _stream_handle(stream)))
+    return res
+
+
+def maxss_align_top(handle: int, seq, offsets, top, pad: int = 100, cigar_stride: int = 512,
+                    out=None, cigar=None, stream=None):
+    """Second phase.  Host form returns (ALN_DTYPE array, list of CIGAR str);
+    device form fills `out` (n*32 bytes) and `cigar` (n*cigar_stride bytes)."""
+    if hasattr(seq, "is_cuda") and seq.is_cuda:
+        r = _reads_struct(seq, offsets, True)
+        _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), _ptr(top), pad, _ptr(out),
+                                     _ptr(cigar), cigar_stride, _stream_handle(stream)))
+        return out, cigar
+    s = _as_u8(seq)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = off.size - 1
+    top = np.ascontiguousarray(top, dtype=TOP2_DTYPE)
+    res = np.zeros(n, dtype=ALN_DTYPE)
+    cig = np.zeros(n * cigar_stride, dtype=np.uint8)
+    r = Reads(s.ctypes.data, off.ctypes.data, n, 0)
+    _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), top.ctypes.data, pad,
+                                 res.ctypes.data, cig.ctypes.data, cigar_stride,
+                                 _stream_handle(stream)))
+    cigars = [decode_cigar(cig, i, cigar_stride) for i in range(n)]
+    return res, cigars
+
+
+def decode_cigar(buf: np.ndarray, i: int, stride: int) -> str:
+    row = buf[i * stride:(i + 1) * stride]
+    z = np.nonzero(row == 0)[0]
+    end = int(z[0]) if z.size else stride
+    return row[:end].tobytes().decode()
+
+
+def h_(handle):
+    if isinstance(handle, Index):
+        return handle.handle
+    return handle
+
+
+class Index:
+    """Owner of a genome index (freed on close / garbage collection)."""
+
+    def __init__(self, genome, frag_len: int, max_read_len: int, match: int = 1,
+                 mismatch: int = -1, gap: int = -2, flags: int = 0):
+        self.handle = maxss_index_genome(genome, frag_len, max_read_len, match, mismatch, gap,
+                                         flags)
+        self.G, self.NF, self.F = maxss_index_info(self.handle)
+        self.max_read_len = max_read_len
+        self.params = dict(match=match, mismatch=mismatch, gap=gap, flags=flags)
+
+    def scan(self, seq, offsets, out=None, stream=None):
+        return maxss_scan_reads(self.handle, seq, offsets, out, stream)
+
+    def align(self, seq, offsets, top, pad: int = 100, cigar_stride: int = 512, out=None,
+              cigar=None, stream=None):
+        return maxss_align_top(self.handle, seq, offsets, top, pad, cigar_stride, out, cigar,
+                               stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            maxss_index_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,333 @@
+// Second phase: Needleman-Wunsch of every read against the region of its best
+// fragment (Methods, "Second phase of MaxSSmap"), HIP, gfx950.
+//
+// One 256-thread block per read (persistent over reads).  The DP is filled row
+// by row (one row per read base); each thread owns a contiguous run of region
+// columns.  Within a row the diagonal and up moves are independent per
+// column; the left move is a max-plus prefix: with g = -gap >= 0,
+//   D[i][j] = max_{j' <= j} (T[j'] - (j - j') g),  T = max(diag, up),
+// so V[j] = D[i][j] + j g is the running maximum of T[j] + j g.  Each thread
+// scans its run, a block-wide exclusive max-scan carries the prefix across
+// threads, and the boundary column D[i][0] = i*gap seeds the carry.
+// Every cell's move (diagonal, up = 'I', left = 'D', in that priority on ties)
+// is stored in 2 bits in a per-block global scratch slab; one thread traces
+// back and writes the run-length CIGAR.
+#include <limits.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace maxss {
+
+static constexpr int kNwThreads = 256;
+
+struct NwArgs {
+  const uint8_t* gcodes;  // genome codes
+  uint64_t G;
+  uint32_t F, NF;
+  const uint8_t* rcodes;  // forward read codes [n][mstride]
+  const uint32_t* lens;
+  uint32_t mstride;
+  const maxss_top2* top;
+  uint32_t n;
+  uint32_t pad;
+  int M, X, gap;
+  int global_mode;
+  uint32_t cw;            // columns per thread (multiple of 4)
+  uint32_t rowbytes;      // bytes of move codes per DP row
+  uint8_t* slab;          // [gridDim.x][m_max][rowbytes]
+  uint32_t m_max;
+  maxss_aln* out;
+  char* cigar;
+  uint64_t cigar_stride;
+};
+
+__device__ inline long long block_excl_max(long long v, long long* sh) {
+  // inclusive max-scan within the wave, then across the 4 waves
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long long x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x = x > y ? x : y;
+  }
+  if (lane == 63) sh[wv] = x;
+  long long ex = __shfl_up(x, 1, 64);
+  __syncthreads();
+  long long carry = LLONG_MIN;
+  for (int w = 0; w < wv; w++) carry = sh[w] > carry ? sh[w] : carry;
+  __syncthreads();
+  if (lane > 0) carry = ex > carry ? ex : carry;
+  return carry;  // max over all threads before this one (LLONG_MIN if none)
+}
+
+__global__ __launch_bounds__(kNwThreads) void nw_kernel(NwArgs a) {
+  extern __shared__ uint8_t sh[];
+  __shared__ long long scan_sh[4];
+  __shared__ long long red_v[4];
+  __shared__ int red_j[4];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t ncols_max = kNwThreads * a.cw;
+  int* rowA = (int*)sh;                            // ncols_max + 1
+  int* rowB = rowA + ncols_max + 1;                // ncols_max + 1
+  uint8_t* lq = (uint8_t*)(rowB + ncols_max + 1);  // m_max
+  uint8_t* lg = lq + a.m_max;                      // ncols_max
+  char* ops = (char*)(lg + ncols_max);             // m_max + ncols_max
+  uint8_t* slab = a.slab + (uint64_t)blockIdx.x * a.m_max * a.rowbytes;
+  const long long g = -(long long)a.gap;
+  for (uint32_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    const uint32_t m = a.lens[i];
+    const int f = a.top[i].frag[0];
+    maxss_aln* o = a.out + i;
+    char* cg = a.cigar + (uint64_t)i * a.cigar_stride;
+    const int strand = a.top[i].strand[0];
+    if (m == 0 || f < 0 || (uint32_t)f >= a.NF || (strand != 0 && strand != 1)) {
+      if (tid == 0) {
+        o->score = 0; o->strand = -1; o->flags = MAXSS_ALN_SKIPPED;
+        o->_pad[0] = o->_pad[1] = 0;
+        o->ref_begin = o->ref_end = -1; o->cigar_len = 0; o->_pad2 = 0;
+        cg[0] = 0;
+      }
+      continue;
+    }
+    const long long start = (long long)f * a.F;
+    long long ra = start - (long long)a.pad;
+    if (ra < 0) ra = 0;
+    long long rb = start + (long long)a.F + (long long)m - 1 + (long long)a.pad;
+    if (rb > (long long)a.G) rb = (long long)a.G;
+    const uint32_t ncols = (uint32_t)(rb - ra);
+    __syncthreads();  // the previous read's traceback is done with LDS
+    const uint8_t* rc = a.rcodes + (uint64_t)i * a.mstride;
+    for (uint32_t k = tid; k < m; k += kNwThreads) {
+      uint8_t c = strand ? rc[m - 1 - k] : rc[k];
+      if (strand) c = c == kN ? kN : (uint8_t)(3 - c);
+      lq[k] = c;
+    }
+    for (uint32_t j = tid; j < ncols; j += kNwThreads) lg[j] = a.gcodes[ra + j];
+    for (uint32_t j = tid; j <= ncols; j += kNwThreads)
+      rowA[j] = a.global_mode ? (int)j * a.gap : 0;
+    __syncthreads();
+    int* prev = rowA;
+    int* cur = rowB;
+    const uint32_t j0 = 1 + tid * a.cw;  // first column of this thread
+    for (uint32_t r = 1; r <= m; r++) {
+      const uint8_t q = lq[r - 1];
+      const int col0 = (int)r * a.gap;
+      // pass 1: this thread's running max of T[j] + j*g
+      long long run = LLONG_MIN;
+      for (uint32_t t = 0; t < a.cw; t++) {
+        const uint32_t j = j0 + t;
+        if (j > ncols) break;
+        const uint8_t gc = lg[j - 1];
+        const int d = prev[j - 1] + ((q == gc && q != kN) ? a.M : a.X);
+        const int u = prev[j] + a.gap;
+        const long long tv = (long long)(d > u ? d : u) + (long long)j * g;
+        run = tv > run ? tv : run;
+      }
+      long long carry = block_excl_max(run, scan_sh);
+      const long long c0 = (long long)col0;  // column 0: V[0] = D[r][0]
+      carry = carry > c0 ? carry : c0;
+      // pass 2: D values and moves
+      uint8_t* mrow = slab + (uint64_t)(r - 1) * a.rowbytes + tid * (a.cw / 4);
+      uint32_t packed = 0;
+      for (uint32_t t = 0; t < a.cw; t++) {
+        const uint32_t j = j0 + t;
+        uint32_t mv = 0;
+        if (j <= ncols) {
+          const uint8_t gc = lg[j - 1];
+          const int d = prev[j - 1] + ((q == gc && q != kN) ? a.M : a.X);
+          const int u = prev[j] + a.gap;
+          const long long tv = (long long)(d > u ? d : u) + (long long)j * g;
+          carry = tv > carry ? tv : carry;
+          const int D = (int)(carry - (long long)j * g);
+          cur[j] = D;
+          mv = (D == d) ? 0u : (D == u ? 1u : 2u);
+        }
+        packed |= mv << (2 * (t & 3));
+        if ((t & 3) == 3) {
+          mrow[t >> 2] = (uint8_t)packed;
+          packed = 0;
+        }
+      }
+      if (tid == 0) cur[0] = col0;
+      __syncthreads();
+      int* tmp = prev; prev = cur; cur = tmp;
+    }
+    // end column: the whole region (global) or the best, smallest column
+    long long bestv = LLONG_MIN;
+    int bestj = 0;
+    if (a.global_mode) {
+      bestv = prev[ncols];
+      bestj = (int)ncols;
+    } else {
+      for (uint32_t j = tid; j <= ncols; j += kNwThreads) {
+        const long long v = prev[j];
+        if (v > bestv) { bestv = v; bestj = (int)j; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        long long v2 = __shfl_xor(bestv, off, 64);
+        int j2 = __shfl_xor(bestj, off, 64);
+        if (v2 > bestv || (v2 == bestv && j2 < bestj)) { bestv = v2; bestj = j2; }
+      }
+      if ((tid & 63) == 0) { red_v[tid >> 6] = bestv; red_j[tid >> 6] = bestj; }
+      __syncthreads();
+      if (tid == 0) {
+        for (int w = 1; w < kNwThreads / 64; w++)
+          if (red_v[w] > bestv || (red_v[w] == bestv && red_j[w] < bestj)) {
+            bestv = red_v[w]; bestj = red_j[w];
+          }
+      }
+    }
+    __threadfence_block();
+    if (tid == 0) {
+      // traceback (moves of row r live in slab row r-1), ops collected backwards
+      uint32_t len = 0;
+      int ii = (int)m, jj = bestj;
+      while (ii > 0 || (a.global_mode && jj > 0)) {
+        uint32_t mv;
+        if (ii == 0) mv = 2;
+        else if (jj == 0) mv = 1;
+        else {
+          const uint32_t t = (uint32_t)(jj - 1);
+          const uint8_t byte = slab[(uint64_t)(ii - 1) * a.rowbytes + (t >> 2)];
+          mv = (byte >> (2 * (t & 3))) & 3u;
+        }
+        if (mv == 0) {
+          const uint8_t q = lq[ii - 1], gc = lg[jj - 1];
+          ops[len++] = (q == gc && q != kN) ? '=' : 'X';
+          ii--; jj--;
+        } else if (mv == 1) {
+          ops[len++] = 'I';
+          ii--;
+        } else {
+          ops[len++] = 'D';
+          jj--;
+        }
+      }
+      // run-length encode forwards
+      uint64_t w = 0;
+      bool trunc = false;
+      for (int p = (int)len - 1; p >= 0;) {
+        const char op = ops[p];
+        int q2 = p;
+        while (q2 >= 0 && ops[q2] == op) q2--;
+        uint32_t run = (uint32_t)(p - q2);
+        char dig[12];
+        int nd = 0;
+        do { dig[nd++] = (char)('0' + run % 10); run /= 10; } while (run);
+        if (w + (uint64_t)nd + 1 + 1 > a.cigar_stride) { trunc = true; break; }
+        while (nd) cg[w++] = dig[--nd];
+        cg[w++] = op;
+        p = q2;
+      }
+      cg[w] = 0;
+      o->score = (int)bestv;
+      o->strand = (int8_t)strand;
+      o->flags = trunc ? MAXSS_ALN_TRUNCATED : 0;
+      o->_pad[0] = o->_pad[1] = 0;
+      o->ref_begin = ra + jj;
+      o->ref_end = ra + bestj;
+      o->cigar_len = (uint32_t)w;
+      o->_pad2 = 0;
+    }
+  }
+}
+
+}  // namespace maxss
+
+using namespace maxss;
+
+extern "C" maxss_status maxss_align_top(const maxss_index* index, const maxss_reads* reads,
+                                        const maxss_top2* top, uint32_t pad, maxss_aln* out,
+                                        char* cigar, uint64_t cigar_stride, void* stream) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  if (!ix || !reads || !top || !out || !cigar) return fail(MAXSS_EINVAL, "NULL argument");
+  if (cigar_stride < 2) return fail(MAXSS_EINVAL, "cigar_stride must be >= 2");
+  if (pad > (1u << 20)) return fail(MAXSS_EINVAL, "pad %u too large", pad);
+  if (reads->n == 0) return MAXSS_OK;
+  if (!reads->seq || !reads->offsets) return fail(MAXSS_EINVAL, "NULL reads");
+  hipStream_t st = (hipStream_t)stream;
+  maxss_status s;
+  if (!reads->on_device && (s = validate_host_reads(ix, reads))) return s;
+  int cur = 0;
+  if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;
+  if (cur != ix->device) return fail(MAXSS_ESTATE, "index lives on device %d, current is %d",
+                                     ix->device, cur);
+  const uint32_t n = reads->n;
+  DeviceReads dr;
+  EncodedReads er;
+  uint8_t* slab = nullptr;
+  maxss_top2* dtop = nullptr;
+  maxss_aln* dout = nullptr;
+  char* dcig = nullptr;
+  do {
+    if ((s = stage_reads(reads, st, &dr))) break;
+    if ((s = encode_reads(ix, dr, st, &er))) break;
+    const uint32_t m_max = ix->p.max_read_len;
+    const uint64_t ncols_need = (uint64_t)ix->F + m_max - 1 + 2ull * pad;
+    uint32_t cw = (uint32_t)((ncols_need + kNwThreads - 1) / kNwThreads);
+    cw = (cw + 3) & ~3u;
+    const uint32_t ncols_max = cw * kNwThreads;
+    const uint32_t rowbytes = ncols_max / 4;
+    const size_t lds = (size_t)2 * (ncols_max + 1) * 4 + m_max + ncols_max + (m_max + ncols_max) + 16;
+    if (lds > 160 * 1024)
+      { s = fail(MAXSS_EINVAL, "NW region too wide for LDS (%zu bytes)", lds); break; }
+    if (lds > 65536 &&
+        (s = check_hip(hipFuncSetAttribute((const void*)nw_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                       "hipFuncSetAttribute(nw_kernel)")))
+      break;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nw_kernel, kNwThreads, lds) != hipSuccess ||
+        occ < 1)
+      occ = 1;
+    uint32_t grid = (uint32_t)ix->num_cu * (uint32_t)occ;
+    if (grid > n) grid = n;
+    if ((s = check_hip(hipMallocAsync((void**)&slab, (size_t)grid * m_max * rowbytes, st),
+                       "alloc NW slab")))
+      break;
+    NwArgs a{};
+    if (reads->on_device) {
+      dtop = const_cast<maxss_top2*>(top);
+      dout = out;
+      dcig = cigar;
+    } else {
+      if ((s = check_hip(hipMallocAsync((void**)&dtop, sizeof(maxss_top2) * n, st), "alloc top")) ||
+          (s = check_hip(hipMallocAsync((void**)&dout, sizeof(maxss_aln) * n, st), "alloc aln")) ||
+          (s = check_hip(hipMallocAsync((void**)&dcig, (size_t)n * cigar_stride, st), "alloc cigar")) ||
+          (s = check_hip(hipMemcpyAsync(dtop, top, sizeof(maxss_top2) * n, hipMemcpyHostToDevice, st),
+                         "copy top")))
+        break;
+    }
+    a.gcodes = ix->codes; a.G = ix->G; a.F = ix->F; a.NF = ix->NF;
+    a.rcodes = er.codes; a.lens = er.lens; a.mstride = er.mstride;
+    a.top = dtop; a.n = n; a.pad = pad;
+    a.M = ix->p.match; a.X = ix->p.mismatch; a.gap = ix->p.gap;
+    a.global_mode = (ix->p.flags & MAXSS_NW_GLOBAL) ? 1 : 0;
+    a.cw = cw; a.rowbytes = rowbytes; a.slab = slab; a.m_max = m_max;
+    a.out = dout; a.cigar = dcig; a.cigar_stride = cigar_stride;
+    {
+      ProfScope prof("nw", st);
+      nw_kernel<<<grid, kNwThreads, lds, st>>>(a);
+    }
+    if ((s = check_hip(hipGetLastError(), "nw_kernel"))) break;
+    if (!reads->on_device) {
+      if ((s = check_hip(hipMemcpyAsync(out, dout, sizeof(maxss_aln) * n, hipMemcpyDeviceToHost, st),
+                         "copy aln")) ||
+          (s = check_hip(hipMemcpyAsync(cigar, dcig, (size_t)n * cigar_stride, hipMemcpyDeviceToHost, st),
+                         "copy cigar")))
+        break;
+    }
+  } while (0);
+  if (slab) (void)hipFreeAsync(slab, st);
+  if (!reads->on_device) {
+    if (dtop) (void)hipFreeAsync(dtop, st);
+    if (dout) (void)hipFreeAsync(dout, st);
+    if (dcig) (void)hipFreeAsync(dcig, st);
+  }
+  release_encoded(&er, st);
+  release_reads(&dr, st);
+  if (!reads->on_device && s == MAXSS_OK) s = check_hip(hipStreamSynchronize(st), "sync");
+  return s;
+}

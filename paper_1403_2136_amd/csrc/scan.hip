@@ -1,0 +1,467 @@
+// First phase: MaxSS scan of every read against every fragment, top-2
+// fragments per read (HIP, gfx950).
+//
+// What is computed (Methods, "Maximum scoring subsequence" and "First phase of
+// MaxSSmap"; Figure 1): for read i, strand s, fragment f and offset o in
+// [0, F), the window starting at p = f*F + o is scored with the maximum
+// scoring subsequence of the substitution scores sigma(q_s[k], g[p+k]),
+// k < m, i.e. the Kadane recurrence H = max(0, H + sigma), B = max(B, H).
+// A fragment's value is the max over (s, o); a read keeps its two best
+// fragments.
+//
+// How (gfx950 design, not the paper's Fermi layout):
+//   * A wave owns 128*NP start offsets of one fragment: lane l holds NP
+//     packed pairs of offsets (l*NP + j, l*NP + j + 64*NP).  The read base of
+//     step k is wave-uniform.
+//   * The two 16-bit substitution scores of a pair come from one v_perm_b32:
+//     the selector word (from the genome, staged in LDS) picks, for each of
+//     the two genome bases, a byte of the step's 8-byte score pool and the
+//     byte's sign extension (pool bytes 1,3,5,7 hold the scores against
+//     A,C,G,T; bytes 0,2 the score and sign of a genome N).
+//   * Kadane runs on packed int16 with a -32768 bias: with H' = H - 32768,
+//     max(0, H + sigma) is exactly the signed-saturating add H' + sigma
+//     (v_pk_add_i16 with clamp) as long as H + sigma stays below 65536, which
+//     max_read_len * match <= 65535 guarantees.  B' = max(B', H') is one
+//     v_pk_max_i16.  So each pair of cells costs three VALU instructions.
+//   * The window of selector words a lane needs slides by one per step; it is
+//     kept in registers (2*NP words) and refilled from LDS every NP steps.
+//   * A persistent grid pulls (read tile x fragment chunk) work items from an
+//     atomic counter; per-read top-2 live in lane-indexed registers; a merge
+//     kernel combines chunks; the two winners are re-scanned exactly for the
+//     representative strand and offset.
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace maxss {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// Selector halfword of a base code: (low byte selector, high byte selector).
+__device__ inline uint32_t sel16(uint32_t code) {
+  // A: (1, 8)  C: (3, 9)  G: (5, 10)  T: (7, 11)  N: (0, 2)
+  return code == kN ? 0x0200u : ((2u * code + 1u) | ((8u + code) << 8));
+}
+
+__device__ inline uint32_t genome_code(const uint32_t* __restrict__ g2,
+                                       const uint32_t* __restrict__ nm, uint64_t Lpad,
+                                       uint64_t P) {
+  if (P >= Lpad) return kN;
+  if ((nm[P >> 5] >> (P & 31)) & 1u) return kN;
+  return (g2[P >> 4] >> (2 * (P & 15))) & 3u;
+}
+
+// LDS slot of window word w: one padding word every NP words, so that the
+// 64 lanes reading words l*NP + c hit 64 distinct banks.
+template <int NP>
+__device__ inline uint32_t phys(uint32_t w) {
+  return w + w / NP;
+}
+
+struct ScanArgs {
+  const uint32_t* g2;
+  const uint32_t* nmask;
+  uint64_t Lpad;
+  uint32_t F, NF, nseg;
+  const uint2* prof;
+  uint32_t mstride;
+  const uint32_t* lens;
+  const uint32_t* order;
+  uint32_t n;
+  uint32_t R, ntiles, C, nchunks;
+  uint32_t total_work;
+  uint32_t* work_ctr;
+  int4* partial;
+  uint32_t nstrands;
+  uint32_t mp_max;  // largest padded read length of the call
+};
+
+template <int NP>
+__device__ inline uint32_t staged_words(uint32_t mp) {
+  return 64u * NP + mp + 2u * NP;
+}
+
+template <int NP>
+size_t scan_lds_bytes(uint32_t mp_max) {
+  uint32_t w = 64u * NP + mp_max + 2u * NP;
+  return (size_t)(w + w / NP + 1) * 4u;
+}
+
+// Kadane over one read strand for this lane's NP offset pairs.  Returns the
+// lane's per-pair maxima (biased by -32768) in B.
+template <int NP>
+__device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t lane,
+                                    const uint2* __restrict__ prof, uint32_t mpad,
+                                    s16x2 (&B)[NP]) {
+  s16x2 H[NP];
+  const s16x2 lo = {(short)-32768, (short)-32768};
+#pragma unroll
+  for (int j = 0; j < NP; j++) {
+    H[j] = lo;
+    B[j] = lo;
+  }
+  const uint32_t lb = lane * NP;
+  uint32_t win[2 * NP];
+  uint32_t nxt[NP];
+#pragma unroll
+  for (int i = 0; i < NP; i++) {
+    win[i] = lds[phys<NP>(lb + i)];
+    nxt[i] = lds[phys<NP>(lb + NP + i)];
+  }
+  for (uint32_t kb = 0; kb < mpad; kb += NP) {
+#pragma unroll
+    for (int i = 0; i < NP; i++) win[NP + i] = nxt[i];
+    // prefetch the next block's new window words (stays inside the staged
+    // range: staged_words covers lb + mpad + 2*NP)
+#pragma unroll
+    for (int i = 0; i < NP; i++) nxt[i] = lds[phys<NP>(lb + kb + 2 * NP + i)];
+    const uint2* pk = prof + kb;
+#pragma unroll
+    for (int t = 0; t < NP; t++) {
+      const uint2 pw = pk[t];
+#pragma unroll
+      for (int j = 0; j < NP; j++) {
+        uint32_t s = __builtin_amdgcn_perm(pw.y, pw.x, win[j + t]);
+        H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, s));
+      }
+#pragma unroll
+      for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < NP; i++) win[i] = win[NP + i];
+  }
+}
+
+__device__ inline int wave_max_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int NP>
+__global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
+  extern __shared__ uint32_t lds[];
+  constexpr uint32_t HALF = 64u * NP, S = 128u * NP;
+  const uint32_t lane = threadIdx.x;
+  for (;;) {
+    uint32_t w = 0;
+    if (lane == 0) w = atomicAdd(a.work_ctr, 1u);
+    w = __builtin_amdgcn_readfirstlane(__shfl(w, 0, 64));
+    if (w >= a.total_work) break;
+    const uint32_t tile = w / a.nchunks, chunk = w - tile * a.nchunks;
+    const uint32_t rbase = tile * a.R;
+    const uint32_t rcount = min(a.R, a.n - rbase);
+    const uint32_t my_read = lane < rcount ? a.order[rbase + lane] : 0u;
+    const uint32_t my_len = lane < rcount ? a.lens[my_read] : 0u;
+    const uint32_t my_mp = (my_len + NP - 1) / NP * NP;
+    const uint32_t mp_tile = (uint32_t)wave_max_i32((int)my_mp);
+    const uint32_t nwords = staged_words<NP>(mp_tile);
+    int t1s = -1, t1f = -1, t2s = -1, t2f = -1;
+    const uint32_t f0 = chunk * a.C, f1 = min(a.NF, f0 + a.C);
+    for (uint32_t f = f0; f < f1; f++) {
+      int fv = -1;  // lane r: value of fragment f for read r
+      for (uint32_t seg = 0; seg < a.nseg; seg++) {
+        const uint64_t base = (uint64_t)f * a.F + (uint64_t)seg * S;
+        __syncthreads();  // previous segment's readers are done with LDS
+        for (uint32_t wd = lane; wd < nwords; wd += 64) {
+          const uint64_t P = base + wd;
+          const uint32_t c0 = genome_code(a.g2, a.nmask, a.Lpad, P);
+          const uint32_t c1 = genome_code(a.g2, a.nmask, a.Lpad, P + HALF);
+          lds[phys<NP>(wd)] = sel16(c0) | (sel16(c1) << 16);
+        }
+        __syncthreads();
+        const bool partial_seg = (uint64_t)(seg + 1) * S > a.F;
+        const int lo_cnt = min(max((int)a.F - (int)(seg * S) - (int)(lane * NP), 0), NP);
+        const int hi_cnt = min(max((int)a.F - (int)(seg * S + HALF) - (int)(lane * NP), 0), NP);
+        for (uint32_t r = 0; r < rcount; r++) {
+          const uint32_t rid = __builtin_amdgcn_readlane(my_read, r);
+          const uint32_t m = __builtin_amdgcn_readlane(my_len, r);
+          if (m == 0) continue;
+          const uint32_t mpad = (m + NP - 1) / NP * NP;
+          uint32_t bm = 0x80008000u;
+          for (uint32_t s = 0; s < a.nstrands; s++) {
+            s16x2 B[NP];
+            kadane_pairs<NP>(lds, lane, a.prof + ((uint64_t)rid * 2 + s) * a.mstride, mpad, B);
+            if (partial_seg) {
+#pragma unroll
+              for (int j = 0; j < NP; j++) {
+                uint32_t b = __builtin_bit_cast(uint32_t, B[j]);
+                if (j >= lo_cnt) b = (b & 0xFFFF0000u) | 0x8000u;
+                if (j >= hi_cnt) b = (b & 0x0000FFFFu) | 0x80000000u;
+                B[j] = __builtin_bit_cast(s16x2, b);
+              }
+            }
+            s16x2 mx = __builtin_bit_cast(s16x2, bm);
+#pragma unroll
+            for (int j = 0; j < NP; j++) mx = __builtin_elementwise_max(mx, B[j]);
+            bm = __builtin_bit_cast(uint32_t, mx);
+          }
+          const int lv = max((int)(short)(bm & 0xFFFFu), (int)(short)(bm >> 16));
+          const int v = wave_max_i32(lv) + 32768;
+          if (lane == r) fv = max(fv, v);
+        }
+      }
+      // fragments arrive in increasing id order: strict '>' keeps the
+      // smallest id among equal values
+      if (lane < rcount && fv >= 0) {
+        if (fv > t1s) {
+          t2s = t1s; t2f = t1f; t1s = fv; t1f = (int)f;
+        } else if (fv > t2s) {
+          t2s = fv; t2f = (int)f;
+        }
+      }
+    }
+    if (lane < rcount) a.partial[(uint64_t)my_read * a.nchunks + chunk] = make_int4(t1s, t1f, t2s, t2f);
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint32_t n) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void iota_kernel(uint32_t* p, uint32_t n) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+// (score desc, fragment asc) order of candidates; negative fragment = none.
+__device__ inline bool better(int s, int f, int bs, int bf) {
+  if (f < 0) return false;
+  if (bf < 0) return true;
+  return s > bs || (s == bs && f < bf);
+}
+
+// Combine the per-chunk top-2 of every read.
+__global__ void merge_kernel(const int4* __restrict__ partial, uint32_t nchunks,
+                             const uint32_t* __restrict__ lens, uint32_t n,
+                             maxss_top2* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  maxss_top2 r;
+  for (int k = 0; k < 6; k++) r._pad[k] = 0;
+  if (lens[i] == 0) {
+    r.frag[0] = MAXSS_READ_INVALID; r.frag[1] = -1;
+    r.score[0] = r.score[1] = -1;
+    r.offset[0] = r.offset[1] = -1;
+    r.strand[0] = r.strand[1] = -1;
+    out[i] = r;
+    return;
+  }
+  int s1 = -1, f1 = -1, s2 = -1, f2 = -1;
+  for (uint32_t c = 0; c < nchunks; c++) {
+    int4 p = partial[(uint64_t)i * nchunks + c];
+    int cs[2] = {p.x, p.z}, cf[2] = {p.y, p.w};
+    for (int t = 0; t < 2; t++) {
+      if (better(cs[t], cf[t], s1, f1)) {
+        s2 = s1; f2 = f1; s1 = cs[t]; f1 = cf[t];
+      } else if (better(cs[t], cf[t], s2, f2)) {
+        s2 = cs[t]; f2 = cf[t];
+      }
+    }
+  }
+  r.frag[0] = f1; r.score[0] = s1;
+  r.frag[1] = f2; r.score[1] = f2 >= 0 ? s2 : -1;
+  r.offset[0] = r.offset[1] = -1;
+  r.strand[0] = r.strand[1] = -1;
+  out[i] = r;
+}
+
+// Exact re-scan of one winning fragment of one read (int32, one offset per
+// thread and strand) to find its representative window: the smallest strand,
+// then the smallest offset, among the windows reaching the fragment's value.
+__global__ __launch_bounds__(256) void rescan_kernel(
+    const uint8_t* __restrict__ gcodes, uint32_t F, const uint8_t* __restrict__ rcodes,
+    const uint32_t* __restrict__ lens, uint32_t mstride, int M, int X, uint32_t nstrands,
+    uint32_t n, maxss_top2* __restrict__ out) {
+  extern __shared__ uint8_t sh[];
+  const uint32_t i = blockIdx.x, which = blockIdx.y;
+  const uint32_t m = lens[i];
+  const int f = out[i].frag[which];
+  if (m == 0 || f < 0) return;
+  uint8_t* lg = sh;                    // F + m - 1 genome codes
+  uint8_t* lq = sh + F + mstride;      // 2*m read codes: forward, reverse complement
+  const uint64_t gb = (uint64_t)f * F;
+  for (uint32_t t = threadIdx.x; t < F + m - 1; t += blockDim.x) lg[t] = gcodes[gb + t];
+  const uint8_t* rc = rcodes + (uint64_t)i * mstride;
+  for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+    uint8_t c = rc[k];
+    lq[k] = c;
+    lq[m + (m - 1 - k)] = c == kN ? kN : (uint8_t)(3 - c);
+  }
+  __syncthreads();
+  uint64_t best = 0;
+  for (uint32_t s = 0; s < nstrands; s++) {
+    const uint8_t* q = lq + s * m;
+    for (uint32_t o = threadIdx.x; o < F; o += blockDim.x) {
+      int H = 0, B = 0;
+      for (uint32_t k = 0; k < m; k++) {
+        const uint8_t g = lg[o + k], c = q[k];
+        H += (g == c && c != kN) ? M : X;
+        H = max(H, 0);
+        B = max(B, H);
+      }
+      const uint64_t key = ((uint64_t)(uint32_t)B << 32) | (0xFFFFFFFFu - (s * F + o));
+      best = key > best ? key : best;
+    }
+  }
+  // block max of the 64-bit keys
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t x = __shfl_xor(best, o, 64);
+    best = x > best ? x : best;
+  }
+  __shared__ uint64_t wbest[4];
+  if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 1; t < (int)(blockDim.x >> 6); t++) best = wbest[t] > best ? wbest[t] : best;
+    const uint32_t code = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFu);
+    out[i].strand[which] = (int8_t)(code / F);
+    out[i].offset[which] = (int32_t)(code % F);
+  }
+}
+
+struct Tiles {
+  int NP;
+  uint32_t R, ntiles, C, nchunks, nseg, grid;
+};
+
+template <int NP>
+static maxss_status launch_scan(const ScanArgs& a, uint32_t grid, size_t lds, hipStream_t st) {
+  ProfScope prof("scan", st);
+  scan_kernel<NP><<<grid, 64, lds, st>>>(a);
+  return check_hip(hipGetLastError(), "scan_kernel");
+}
+
+static size_t lds_for(int NP, uint32_t mp) {
+  switch (NP) {
+    case 8: return scan_lds_bytes<8>(mp);
+    case 16: return scan_lds_bytes<16>(mp);
+    default: return scan_lds_bytes<32>(mp);
+  }
+}
+
+static int occupancy_for(int NP, size_t lds) {
+  int blocks = 0;
+  hipError_t e;
+  switch (NP) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_kernel<8>, 64, lds); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_kernel<16>, 64, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_kernel<32>, 64, lds); break;
+  }
+  if (e != hipSuccess || blocks < 1) blocks = 1;
+  return blocks;
+}
+
+// Tile shape: the widest wave segment (128*NP offsets) that divides F, read
+// tiles of R reads and enough fragment chunks to give every resident wave
+// several work items.
+static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mp_max) {
+  Tiles t{};
+  const uint32_t F = ix->F;
+  if (F % 4096 == 0) t.NP = 32;
+  else if (F % 2048 == 0) t.NP = 16;
+  else t.NP = 8;
+  const uint32_t S = 128u * t.NP;
+  t.nseg = (F + S - 1) / S;
+  const size_t lds = lds_for(t.NP, mp_max);
+  const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, lds);
+  t.R = 32;
+  while (t.R > 4 && (uint64_t)((n + t.R - 1) / t.R) * ix->NF < 4ull * resident) t.R /= 2;
+  t.ntiles = (n + t.R - 1) / t.R;
+  uint32_t want = (uint32_t)((4ull * resident + t.ntiles - 1) / t.ntiles);
+  if (want < 1) want = 1;
+  if (want > ix->NF) want = ix->NF;
+  t.C = (ix->NF + want - 1) / want;
+  t.nchunks = (ix->NF + t.C - 1) / t.C;
+  uint64_t total = (uint64_t)t.ntiles * t.nchunks;
+  t.grid = (uint32_t)(total < resident ? total : resident);
+  if (t.grid < 1) t.grid = 1;
+  return t;
+}
+
+}  // namespace maxss
+
+using namespace maxss;
+
+extern "C" maxss_status maxss_scan_reads(const maxss_index* index, const maxss_reads* reads,
+                                         maxss_top2* out, void* stream) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  if (!ix || !reads || !out) return fail(MAXSS_EINVAL, "NULL argument");
+  if (reads->n == 0) return MAXSS_OK;
+  if (!reads->seq || !reads->offsets) return fail(MAXSS_EINVAL, "NULL reads");
+  hipStream_t st = (hipStream_t)stream;
+  maxss_status s;
+  if (!reads->on_device && (s = validate_host_reads(ix, reads))) return s;
+  int cur = 0;
+  if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;
+  if (cur != ix->device) return fail(MAXSS_ESTATE, "index lives on device %d, current is %d",
+                                     ix->device, cur);
+  DeviceReads dr;
+  EncodedReads er;
+  uint32_t* order = nullptr;
+  uint32_t* ctr = nullptr;
+  int4* partial = nullptr;
+  maxss_top2* dout = nullptr;
+  const uint32_t n = reads->n;
+  const uint32_t nstrands = (ix->p.flags & MAXSS_ONE_STRAND) ? 1u : 2u;
+  do {
+    if ((s = stage_reads(reads, st, &dr))) break;
+    if ((s = encode_reads(ix, dr, st, &er))) break;
+    const uint32_t mp_max = er.mstride;
+    Tiles t = choose_tiles(ix, n, mp_max);
+    if ((s = check_hip(hipMallocAsync((void**)&order, sizeof(uint32_t) * n, st), "alloc order")))
+      break;
+    if ((s = check_hip(hipMallocAsync((void**)&ctr, sizeof(uint32_t), st), "alloc counter")))
+      break;
+    if ((s = check_hip(hipMallocAsync((void**)&partial, sizeof(int4) * (uint64_t)n * t.nchunks, st),
+                       "alloc partial")))
+      break;
+    if (reads->on_device) {
+      dout = out;
+    } else if ((s = check_hip(hipMallocAsync((void**)&dout, sizeof(maxss_top2) * n, st),
+                              "alloc out"))) {
+      break;
+    }
+    iota_kernel<<<(n + 255) / 256, 256, 0, st>>>(order, n);
+    fill_u32_kernel<<<1, 64, 0, st>>>(ctr, 0u, 1u);
+    ScanArgs a{};
+    a.g2 = ix->g2; a.nmask = ix->nmask; a.Lpad = ix->Lpad;
+    a.F = ix->F; a.NF = ix->NF; a.nseg = t.nseg;
+    a.prof = er.prof; a.mstride = er.mstride; a.lens = er.lens; a.order = order; a.n = n;
+    a.R = t.R; a.ntiles = t.ntiles; a.C = t.C; a.nchunks = t.nchunks;
+    a.total_work = t.ntiles * t.nchunks; a.work_ctr = ctr; a.partial = partial;
+    a.nstrands = nstrands; a.mp_max = mp_max;
+    const size_t lds = lds_for(t.NP, mp_max);
+    if (t.NP == 8) s = launch_scan<8>(a, t.grid, lds, st);
+    else if (t.NP == 16) s = launch_scan<16>(a, t.grid, lds, st);
+    else s = launch_scan<32>(a, t.grid, lds, st);
+    if (s) break;
+    {
+      ProfScope prof("merge", st);
+      merge_kernel<<<(n + 255) / 256, 256, 0, st>>>(partial, t.nchunks, er.lens, n, dout);
+    }
+    if ((s = check_hip(hipGetLastError(), "merge_kernel"))) break;
+    const size_t rl = (size_t)ix->F + er.mstride + 2 * er.mstride + 16;
+    {
+      ProfScope prof("rescan", st);
+      rescan_kernel<<<dim3(n, 2), 256, rl, st>>>(ix->codes, ix->F, er.codes, er.lens, er.mstride,
+                                                 ix->p.match, ix->p.mismatch, nstrands, n, dout);
+    }
+    if ((s = check_hip(hipGetLastError(), "rescan_kernel"))) break;
+    if (!reads->on_device) {
+      if ((s = check_hip(hipMemcpyAsync(out, dout, sizeof(maxss_top2) * n, hipMemcpyDeviceToHost, st),
+                         "copy results")))
+        break;
+    }
+  } while (0);
+  if (order) (void)hipFreeAsync(order, st);
+  if (ctr) (void)hipFreeAsync(ctr, st);
+  if (partial) (void)hipFreeAsync(partial, st);
+  if (dout && dout != out) (void)hipFreeAsync(dout, st);
+  release_encoded(&er, st);
+  release_reads(&dr, st);
+  if (!reads->on_device && s == MAXSS_OK) s = check_hip(hipStreamSynchronize(st), "sync");
+  return s;
+}
