@@ -144,27 +144,17 @@ __device__ inline uint8_t dev_code(char c) {
   }
 }
 
-// Scan pool of one read position: two 32-bit words holding, as int8, the
-// substitution score of the read base q against A, C, G, T (bytes 1, 3, 5, 7,
-// whose sign-extension selectors 8..11 v_perm_b32 provides) and, for a genome
-// N, the mismatch score and its sign byte (bytes 0 and 2).
-__device__ inline uint2 pool_words(uint8_t q, int M, int X) {
-  uint32_t x8 = (uint32_t)(X & 0xFF), sx = X < 0 ? 0xFFu : 0u;
-  uint32_t sA = (q == kA ? (uint32_t)(M & 0xFF) : x8);
-  uint32_t sC = (q == kC ? (uint32_t)(M & 0xFF) : x8);
-  uint32_t sG = (q == kG ? (uint32_t)(M & 0xFF) : x8);
-  uint32_t sT = (q == kT ? (uint32_t)(M & 0xFF) : x8);
-  uint2 w;
-  w.x = x8 | (sA << 8) | (sx << 16) | (sC << 24);  // pool bytes 0..3
-  w.y = (sG << 8) | (sT << 24);                    // pool bytes 4..7
-  return w;
-}
+// Pool-shift code of a read base: which byte of the scan's 8-byte score pool
+// holds the score against the genome base equal to it (A 1, C 3, G 5, T 7);
+// N gets byte 4, which no genome selector reads, so it mismatches everything.
+__device__ inline uint32_t pool_shift_code(uint8_t q) { return q == kN ? 4u : 2u * q + 1u; }
 
-// One wave per read: validity (length and characters), forward codes, and the
-// scan pools of both strands for positions [0, mstride) (N past the end).
+// One wave per read: validity (length and characters), forward base codes,
+// and the 4-bit pool-shift codes of both strands for positions [0, mstride)
+// (N past the end).
 __global__ __launch_bounds__(256) void encode_reads_kernel(
     const char* __restrict__ seq, const uint64_t* __restrict__ off, uint32_t n,
-    uint32_t max_len, uint32_t mstride, int M, int X, uint2* __restrict__ prof,
+    uint32_t max_len, uint32_t mstride, uint32_t* __restrict__ sel4,
     uint8_t* __restrict__ codes, uint32_t* __restrict__ lens) {
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t lane = threadIdx.x & 63;
@@ -176,37 +166,43 @@ __global__ __launch_bounds__(256) void encode_reads_kernel(
   bool bad = false;
   for (uint32_t k = lane; k < m; k += 64) bad |= dev_code(seq[a + k]) == 0xFF;
   ok = ok && !__any(bad);
-  uint2* pf = prof + (uint64_t)wave * 2 * mstride;
-  uint2* pr = pf + mstride;
+  const uint32_t nw = mstride / 8;
+  uint32_t* sf = sel4 + (uint64_t)wave * 2 * nw;
+  uint32_t* sr = sf + nw;
   uint8_t* cf = codes + (uint64_t)wave * mstride;
-  for (uint32_t k = lane; k < mstride; k += 64) {
-    uint8_t qf = kN, qr = kN;
-    if (ok && k < m) {
-      qf = dev_code(seq[a + k]);
-      uint8_t c = dev_code(seq[a + (m - 1 - k)]);
-      qr = c == kN ? kN : (uint8_t)(3 - c);  // complement: A<->T, C<->G
+  for (uint32_t w = lane; w < nw; w += 64) {
+    uint32_t wf = 0, wr = 0;
+    for (uint32_t t = 0; t < 8; t++) {
+      const uint32_t k = 8 * w + t;
+      uint8_t qf = kN, qr = kN;
+      if (ok && k < m) {
+        qf = dev_code(seq[a + k]);
+        const uint8_t c = dev_code(seq[a + (m - 1 - k)]);
+        qr = c == kN ? kN : (uint8_t)(3 - c);  // complement: A<->T, C<->G
+      }
+      wf |= pool_shift_code(qf) << (4 * t);
+      wr |= pool_shift_code(qr) << (4 * t);
+      cf[k] = qf;
     }
-    pf[k] = pool_words(qf, M, X);
-    pr[k] = pool_words(qr, M, X);
-    cf[k] = qf;
+    sf[w] = wf;
+    sr[w] = wr;
   }
   if (lane == 0) lens[wave] = ok ? m : 0;
 }
 
-// Profiles are read up to one unrolled block past a read's padded length.
-static constexpr uint32_t kProfSlack = 64;
+static constexpr uint32_t kSlack = 64;
 
 maxss_status encode_reads(const Index* ix, const DeviceReads& r, hipStream_t st,
                           EncodedReads* e) {
   e->mstride = read_stride(ix);
   uint64_t n = r.n;
   maxss_status s;
-  if ((s = check_hip(hipMallocAsync((void**)&e->prof,
-                                    sizeof(uint2) * (n * 2 * e->mstride + kProfSlack), st),
-                     "hipMallocAsync(profiles)")))
-    return s;
-  if ((s = check_hip(hipMallocAsync((void**)&e->codes, n * e->mstride + kProfSlack, st),
+  if ((s = check_hip(hipMallocAsync((void**)&e->sel4,
+                                    sizeof(uint32_t) * (n * 2 * (e->mstride / 8) + kSlack), st),
                      "hipMallocAsync(read codes)")))
+    return s;
+  if ((s = check_hip(hipMallocAsync((void**)&e->codes, n * e->mstride + kSlack, st),
+                     "hipMallocAsync(read bases)")))
     return s;
   if ((s = check_hip(hipMallocAsync((void**)&e->lens, sizeof(uint32_t) * (n + 1), st),
                      "hipMallocAsync(lens)")))
@@ -214,16 +210,15 @@ maxss_status encode_reads(const Index* ix, const DeviceReads& r, hipStream_t st,
   uint32_t blocks = (uint32_t)((n * 64 + 255) / 256);
   ProfScope prof("encode", st);
   encode_reads_kernel<<<blocks, 256, 0, st>>>(r.seq, r.off, r.n, ix->p.max_read_len,
-                                              e->mstride, ix->p.match, ix->p.mismatch, e->prof,
-                                              e->codes, e->lens);
+                                              e->mstride, e->sel4, e->codes, e->lens);
   return check_hip(hipGetLastError(), "encode_reads_kernel");
 }
 
 void release_encoded(EncodedReads* e, hipStream_t st) {
-  if (e->prof) (void)hipFreeAsync(e->prof, st);
+  if (e->sel4) (void)hipFreeAsync(e->sel4, st);
   if (e->codes) (void)hipFreeAsync(e->codes, st);
   if (e->lens) (void)hipFreeAsync(e->lens, st);
-  e->prof = nullptr;
+  e->sel4 = nullptr;
   e->codes = nullptr;
   e->lens = nullptr;
 }

@@ -61,12 +61,18 @@ maxss_status validate_host_reads(const Index* ix, const maxss_reads* r);
 maxss_status stage_reads(const maxss_reads* r, hipStream_t st, DeviceReads* out);
 void release_reads(DeviceReads* d, hipStream_t st);
 
-// Encoded reads for one call: per read and strand, mstride profile entries
-// (two 32-bit pool words per position), plus forward codes and lengths.
+// Encoded reads for one call.
+//   sel4  : per read and strand, mstride/8 words of 4-bit pool-shift codes,
+//           8 positions per word (position k at bits 4*(k%8)): the byte of the
+//           scan's score pool that the read base turns into a match score
+//           (A 1, C 3, G 5, T 7; N and the padding past the read 4, a byte no
+//           genome selector reads).
+//   codes : forward-strand base codes (kA..kN), kN past the end.
+//   lens  : read lengths, 0 for an invalid read.
 struct EncodedReads {
-  uint2* prof = nullptr;     // [n][2][mstride] (+ slack)
-  uint8_t* codes = nullptr;  // [n][mstride] forward-strand codes, kN past the end
-  uint32_t* lens = nullptr;  // [n], 0 = invalid read
+  uint32_t* sel4 = nullptr;  // [n][2][mstride/8]
+  uint8_t* codes = nullptr;  // [n][mstride]
+  uint32_t* lens = nullptr;  // [n]
   uint32_t mstride = 0;
 };
 

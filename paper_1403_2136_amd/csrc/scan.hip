@@ -17,7 +17,9 @@
 //     the selector word (from the genome, staged in LDS) picks, for each of
 //     the two genome bases, a byte of the step's 8-byte score pool and the
 //     byte's sign extension (pool bytes 1,3,5,7 hold the scores against
-//     A,C,G,T; bytes 0,2 the score and sign of a genome N).
+//     A,C,G,T; bytes 0,2 the score and sign of a genome N).  The pool is
+//     built on the scalar unit from the read base's 4-bit code, staged in
+//     LDS per read tile: pool = all-mismatch pool ^ ((M ^ X) << 8*code).
 //   * Kadane runs on packed int16 with a -32768 bias: with H' = H - 32768,
 //     max(0, H + sigma) is exactly the signed-saturating add H' + sigma
 //     (v_pk_add_i16 with clamp) as long as H + sigma stays below 65536, which
@@ -29,7 +31,10 @@
 //     atomic counter; per-read top-2 live in lane-indexed registers; a merge
 //     kernel combines chunks; the two winners are re-scanned exactly for the
 //     representative strand and offset.
+#include <math.h>
 #include <stdint.h>
+
+#include <cmath>
 
 #include "internal.h"
 
@@ -63,8 +68,12 @@ struct ScanArgs {
   const uint32_t* nmask;
   uint64_t Lpad;
   uint32_t F, NF, nseg;
-  const uint2* prof;
-  uint32_t mstride;
+  const uint32_t* sel4;   // [n][2][cwg] 4-bit pool-shift codes
+  uint32_t cwg;           // code words per read strand in sel4 (mstride / 8)
+  uint32_t cw;            // code words per read strand in LDS (cwg + NP / 8 + 1)
+  uint32_t win_slots;     // LDS words reserved for the genome window
+  uint64_t xpool;         // all-mismatch score pool
+  uint64_t dpool;         // (M ^ X) & 0xFF: flips one pool byte to the match score
   const uint32_t* lens;
   const uint32_t* order;
   uint32_t n;
@@ -81,18 +90,56 @@ __device__ inline uint32_t staged_words(uint32_t mp) {
   return 64u * NP + mp + 2u * NP;
 }
 
-template <int NP>
-size_t scan_lds_bytes(uint32_t mp_max) {
-  uint32_t w = 64u * NP + mp_max + 2u * NP;
-  return (size_t)(w + w / NP + 1) * 4u;
+// LDS words the genome window of a tile needs (with the bank padding).
+inline uint32_t win_slots_for(int NP, uint32_t mp_max) {
+  const uint32_t w = 64u * NP + mp_max + 2u * NP;
+  return w + w / NP + 1;
 }
 
-// Kadane over one read strand for this lane's NP offset pairs.  Returns the
-// lane's per-pair maxima (biased by -32768) in B.
+// 8 codes (4 bits each) of positions [k, k+8) of a strand, from its LDS code
+// words (uniform; scalar after readfirstlane).
+__device__ inline uint32_t codes8(const uint32_t* __restrict__ lc, uint32_t k) {
+  const uint32_t w = k >> 3, sh = 4u * (k & 7u);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(lc[w]);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(lc[w + 1]);
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+}
+
+// SUB Kadane steps (SUB <= 8) starting at read position k, with the window
+// loaded from LDS for exactly these steps.
+template <int NP, int SUB>
+__device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lb,
+                                  const uint32_t* __restrict__ lc, uint32_t k, uint64_t xpool,
+                                  uint64_t dpool, s16x2 (&H)[NP], s16x2 (&B)[NP]) {
+  uint32_t win[NP + SUB - 1];
+#pragma unroll
+  for (int i = 0; i < NP + SUB - 1; i++) win[i] = lds[phys<NP>(lb + k + i)];
+  const uint32_t cc = codes8(lc, k);
+#pragma unroll
+  for (int t = 0; t < SUB; t++) {
+    const uint32_t c = (cc >> (4 * t)) & 15u;
+    const uint64_t pool = xpool ^ (dpool << (c << 3));
+    const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
+#pragma unroll
+    for (int j = 0; j < NP; j++) {
+      uint32_t sg = __builtin_amdgcn_perm(phi, plo, win[j + t]);
+      H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
+    }
+#pragma unroll
+    for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
+  }
+}
+
+// Kadane over one read strand of length m for this lane's NP offset pairs.
+// lc: the strand's 4-bit codes in LDS.  The first m % NP steps run as
+// unrolled sub-blocks of 8/4/2/1 steps, the rest as full NP-step blocks, so
+// no padding step is computed.  Returns the lane's per-pair maxima (biased by
+// -32768) in B.
 template <int NP>
 __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t lane,
-                                    const uint2* __restrict__ prof, uint32_t mpad,
-                                    s16x2 (&B)[NP]) {
+                                    const uint32_t* __restrict__ lc, uint32_t m,
+                                    uint64_t xpool, uint64_t dpool, s16x2 (&B)[NP]) {
+  constexpr int CW = NP / 8;
   s16x2 H[NP];
   const s16x2 lo = {(short)-32768, (short)-32768};
 #pragma unroll
@@ -101,28 +148,54 @@ __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t l
     B[j] = lo;
   }
   const uint32_t lb = lane * NP;
+  const uint32_t rem = m % NP;
+  uint32_t k = 0;
+  if (NP > 16 && (rem & 16)) {
+    kadane_sub<NP, 8>(lds, lb, lc, k, xpool, dpool, H, B);
+    kadane_sub<NP, 8>(lds, lb, lc, k + 8, xpool, dpool, H, B);
+    k += 16;
+  }
+  if (NP > 8 && (rem & 8)) { kadane_sub<NP, 8>(lds, lb, lc, k, xpool, dpool, H, B); k += 8; }
+  if (rem & 4) { kadane_sub<NP, 4>(lds, lb, lc, k, xpool, dpool, H, B); k += 4; }
+  if (rem & 2) { kadane_sub<NP, 2>(lds, lb, lc, k, xpool, dpool, H, B); k += 2; }
+  if (rem & 1) { kadane_sub<NP, 1>(lds, lb, lc, k, xpool, dpool, H, B); k += 1; }
+  if (k >= m) return;
+  // full blocks from k = rem; codes realigned by 4*(k%8) bits
+  const uint32_t csh = 4u * (k & 7u);
   uint32_t win[2 * NP];
   uint32_t nxt[NP];
+  uint32_t cn[CW + 1];
 #pragma unroll
   for (int i = 0; i < NP; i++) {
-    win[i] = lds[phys<NP>(lb + i)];
-    nxt[i] = lds[phys<NP>(lb + NP + i)];
+    win[i] = lds[phys<NP>(lb + k + i)];
+    nxt[i] = lds[phys<NP>(lb + k + NP + i)];
   }
-  for (uint32_t kb = 0; kb < mpad; kb += NP) {
+#pragma unroll
+  for (int i = 0; i <= CW; i++) cn[i] = __builtin_amdgcn_readfirstlane(lc[(k >> 3) + i]);
+  for (uint32_t kb = k; kb < m; kb += NP) {
+    uint32_t cc[CW];
+#pragma unroll
+    for (int i = 0; i < CW; i++)
+      cc[i] = (uint32_t)((((uint64_t)cn[i + 1] << 32) | cn[i]) >> csh);
 #pragma unroll
     for (int i = 0; i < NP; i++) win[NP + i] = nxt[i];
-    // prefetch the next block's new window words (stays inside the staged
-    // range: staged_words covers lb + mpad + 2*NP)
+    // prefetch the next block's window words and code words (inside the
+    // staged ranges: the window covers lb + m + 2*NP words, the codes
+    // m/8 + NP/8 + 1 words)
 #pragma unroll
     for (int i = 0; i < NP; i++) nxt[i] = lds[phys<NP>(lb + kb + 2 * NP + i)];
-    const uint2* pk = prof + kb;
+#pragma unroll
+    for (int i = 0; i <= CW; i++)
+      cn[i] = __builtin_amdgcn_readfirstlane(lc[((kb + NP) >> 3) + i]);
 #pragma unroll
     for (int t = 0; t < NP; t++) {
-      const uint2 pw = pk[t];
+      const uint32_t c = (cc[t >> 3] >> (4 * (t & 7))) & 15u;
+      const uint64_t pool = xpool ^ (dpool << (c << 3));
+      const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
 #pragma unroll
       for (int j = 0; j < NP; j++) {
-        uint32_t s = __builtin_amdgcn_perm(pw.y, pw.x, win[j + t]);
-        H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, s));
+        uint32_t sg = __builtin_amdgcn_perm(phi, plo, win[j + t]);
+        H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
       }
 #pragma unroll
       for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
@@ -143,12 +216,15 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t HALF = 64u * NP, S = 128u * NP;
   const uint32_t lane = threadIdx.x;
+  uint32_t* lcodes = lds + a.win_slots;
   for (;;) {
     uint32_t w = 0;
     if (lane == 0) w = atomicAdd(a.work_ctr, 1u);
     w = __builtin_amdgcn_readfirstlane(__shfl(w, 0, 64));
     if (w >= a.total_work) break;
-    const uint32_t tile = w / a.nchunks, chunk = w - tile * a.nchunks;
+    // chunk-major order: every tile of chunk 0, then chunk 1, ...; the last
+    // (shortest) chunk and, within a chunk, the shortest tiles come last
+    const uint32_t chunk = w / a.ntiles, tile = w - chunk * a.ntiles;
     const uint32_t rbase = tile * a.R;
     const uint32_t rcount = min(a.R, a.n - rbase);
     const uint32_t my_read = lane < rcount ? a.order[rbase + lane] : 0u;
@@ -158,6 +234,14 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
     const uint32_t nwords = staged_words<NP>(mp_tile);
     int t1s = -1, t1f = -1, t2s = -1, t2f = -1;
     const uint32_t f0 = chunk * a.C, f1 = min(a.NF, f0 + a.C);
+    // the tile's read codes, both strands, into LDS (N-padded to cw words)
+    __syncthreads();
+    for (uint32_t idx = lane; idx < rcount * 2 * a.cw; idx += 64) {
+      const uint32_t r = idx / (2 * a.cw), rem = idx - r * 2 * a.cw;
+      const uint32_t s = rem / a.cw, wd = rem - s * a.cw;
+      const uint32_t rid = a.order[rbase + r];
+      lcodes[idx] = wd < a.cwg ? a.sel4[((uint64_t)rid * 2 + s) * a.cwg + wd] : 0x44444444u;
+    }
     for (uint32_t f = f0; f < f1; f++) {
       int fv = -1;  // lane r: value of fragment f for read r
       for (uint32_t seg = 0; seg < a.nseg; seg++) {
@@ -174,14 +258,12 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
         const int lo_cnt = min(max((int)a.F - (int)(seg * S) - (int)(lane * NP), 0), NP);
         const int hi_cnt = min(max((int)a.F - (int)(seg * S + HALF) - (int)(lane * NP), 0), NP);
         for (uint32_t r = 0; r < rcount; r++) {
-          const uint32_t rid = __builtin_amdgcn_readlane(my_read, r);
           const uint32_t m = __builtin_amdgcn_readlane(my_len, r);
           if (m == 0) continue;
-          const uint32_t mpad = (m + NP - 1) / NP * NP;
           uint32_t bm = 0x80008000u;
           for (uint32_t s = 0; s < a.nstrands; s++) {
             s16x2 B[NP];
-            kadane_pairs<NP>(lds, lane, a.prof + ((uint64_t)rid * 2 + s) * a.mstride, mpad, B);
+            kadane_pairs<NP>(lds, lane, lcodes + (r * 2 + s) * a.cw, m, a.xpool, a.dpool, B);
             if (partial_seg) {
 #pragma unroll
               for (int j = 0; j < NP; j++) {
@@ -220,9 +302,46 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint32_t n) {
   if (i < n) p[i] = v;
 }
 
-__global__ void iota_kernel(uint32_t* p, uint32_t n) {
+// Counting sort of the reads by length, longest first (invalid reads, length
+// 0, last).  Ties are placed in atomic order: the order only shapes the read
+// tiles, never a result.
+__global__ void len_hist_kernel(const uint32_t* __restrict__ lens, uint32_t n,
+                                uint32_t* __restrict__ hist) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = i;
+  if (i < n) atomicAdd(&hist[lens[i]], 1u);
+}
+
+// hist[L] -> first output position of length L in descending-length order.
+// One block of 1024 threads; nb = number of bins (max length + 1).
+__global__ __launch_bounds__(1024) void len_starts_kernel(uint32_t* __restrict__ hist,
+                                                          uint32_t nb) {
+  __shared__ uint32_t part[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (nb + 1023) / 1024;
+  // thread t owns bins (descending length) [t*per, (t+1)*per)
+  uint32_t sum = 0;
+  for (uint32_t k = t * per; k < min(nb, (t + 1) * per); k++) sum += hist[nb - 1 - k];
+  part[t] = sum;
+  __syncthreads();
+  for (uint32_t o = 1; o < 1024; o <<= 1) {
+    uint32_t v = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;  // exclusive prefix
+  for (uint32_t k = t * per; k < min(nb, (t + 1) * per); k++) {
+    const uint32_t L = nb - 1 - k;
+    const uint32_t c = hist[L];
+    hist[L] = run;
+    run += c;
+  }
+}
+
+__global__ void len_scatter_kernel(const uint32_t* __restrict__ lens, uint32_t n,
+                                   uint32_t* __restrict__ starts, uint32_t* __restrict__ order) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) order[atomicAdd(&starts[lens[i]], 1u)] = i;
 }
 
 // (score desc, fragment asc) order of candidates; negative fragment = none.
@@ -324,21 +443,22 @@ __global__ __launch_bounds__(256) void rescan_kernel(
 struct Tiles {
   int NP;
   uint32_t R, ntiles, C, nchunks, nseg, grid;
+  uint32_t win_slots, cw;
+  size_t lds;
 };
 
 template <int NP>
 static maxss_status launch_scan(const ScanArgs& a, uint32_t grid, size_t lds, hipStream_t st) {
+  if (lds > 65536) {
+    maxss_status s = check_hip(hipFuncSetAttribute((const void*)scan_kernel<NP>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)lds),
+                               "hipFuncSetAttribute(scan_kernel)");
+    if (s) return s;
+  }
   ProfScope prof("scan", st);
   scan_kernel<NP><<<grid, 64, lds, st>>>(a);
   return check_hip(hipGetLastError(), "scan_kernel");
-}
-
-static size_t lds_for(int NP, uint32_t mp) {
-  switch (NP) {
-    case 8: return scan_lds_bytes<8>(mp);
-    case 16: return scan_lds_bytes<16>(mp);
-    default: return scan_lds_bytes<32>(mp);
-  }
 }
 
 static int occupancy_for(int NP, size_t lds) {
@@ -353,10 +473,13 @@ static int occupancy_for(int NP, size_t lds) {
   return blocks;
 }
 
+// Per-wave LDS budget of the scan: the genome window plus the tile's codes.
+static constexpr size_t kScanLdsBudget = 40 * 1024;
+
 // Tile shape: the widest wave segment (128*NP offsets) that divides F, read
-// tiles of R reads and enough fragment chunks to give every resident wave
-// several work items.
-static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mp_max) {
+// tiles of R reads (bounded by the LDS budget) and enough fragment chunks to
+// give every resident wave several work items.
+static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride) {
   Tiles t{};
   const uint32_t F = ix->F;
   if (F % 4096 == 0) t.NP = 32;
@@ -364,15 +487,42 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mp_max) {
   else t.NP = 8;
   const uint32_t S = 128u * t.NP;
   t.nseg = (F + S - 1) / S;
-  const size_t lds = lds_for(t.NP, mp_max);
-  const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, lds);
+  t.win_slots = win_slots_for(t.NP, mstride);
+  t.cw = mstride / 8 + (uint32_t)t.NP / 8 + 1;
+  const size_t win_bytes = (size_t)t.win_slots * 4u;
+  const size_t per_read = (size_t)2 * t.cw * 4u;
   t.R = 32;
+  while (t.R > 1 && win_bytes + t.R * per_read > kScanLdsBudget) t.R /= 2;
+  t.lds = win_bytes + t.R * per_read;
+  const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.lds);
   while (t.R > 4 && (uint64_t)((n + t.R - 1) / t.R) * ix->NF < 4ull * resident) t.R /= 2;
+  t.lds = win_bytes + t.R * per_read;
   t.ntiles = (n + t.R - 1) / t.R;
-  uint32_t want = (uint32_t)((4ull * resident + t.ntiles - 1) / t.ntiles);
-  if (want < 1) want = 1;
-  if (want > ix->NF) want = ix->NF;
-  t.C = (ix->NF + want - 1) / want;
+  // Chunk count: items of equal cost run in rounds of `resident` waves, so
+  // pick the count whose item total best fills whole rounds (at least 8
+  // rounds when the work allows it; fewer, larger items on ties).
+  uint32_t best_c = 1;
+  double best_eff = -1.0;
+  const uint64_t min_items = 8ull * resident;
+  uint32_t c_lo = (uint32_t)((min_items + t.ntiles - 1) / t.ntiles);
+  if (c_lo < 1) c_lo = 1;
+  if (c_lo > ix->NF) c_lo = ix->NF;
+  const uint32_t c_hi = c_lo * 4 < ix->NF ? c_lo * 4 : ix->NF;
+  for (uint32_t c = c_lo; c <= c_hi; c++) {
+    const uint32_t C = (ix->NF + c - 1) / c;
+    const uint32_t nch = (ix->NF + C - 1) / C;
+    const double full = (double)t.ntiles * (nch - 1) * C +
+                        (double)t.ntiles * (ix->NF - (uint64_t)(nch - 1) * C);
+    const double unit = (double)C;  // cost of one full item, in fragments
+    const double per_wave = full / resident;
+    const double rounds = std::ceil(per_wave / unit - 1e-9);
+    const double eff = per_wave / (rounds * unit);
+    if (eff > best_eff + 1e-3) {
+      best_eff = eff;
+      best_c = nch;
+    }
+  }
+  t.C = (ix->NF + best_c - 1) / best_c;
   t.nchunks = (ix->NF + t.C - 1) / t.C;
   uint64_t total = (uint64_t)t.ntiles * t.nchunks;
   t.grid = (uint32_t)(total < resident ? total : resident);
@@ -411,6 +561,11 @@ extern "C" maxss_status maxss_scan_reads(const maxss_index* index, const maxss_r
     if ((s = encode_reads(ix, dr, st, &er))) break;
     const uint32_t mp_max = er.mstride;
     Tiles t = choose_tiles(ix, n, mp_max);
+    const uint32_t M8 = (uint32_t)ix->p.match & 0xFFu, X8 = (uint32_t)ix->p.mismatch & 0xFFu;
+    const uint64_t sx = ix->p.mismatch < 0 ? 0xFFull : 0ull;
+    // all-mismatch pool: bytes [X, X, sign(X), X, 0, X, 0, X]
+    const uint64_t xpool = (uint64_t)X8 | ((uint64_t)X8 << 8) | (sx << 16) | ((uint64_t)X8 << 24) |
+                           ((uint64_t)X8 << 40) | ((uint64_t)X8 << 56);
     if ((s = check_hip(hipMallocAsync((void**)&order, sizeof(uint32_t) * n, st), "alloc order")))
       break;
     if ((s = check_hip(hipMallocAsync((void**)&ctr, sizeof(uint32_t), st), "alloc counter")))
@@ -424,16 +579,28 @@ extern "C" maxss_status maxss_scan_reads(const maxss_index* index, const maxss_r
                               "alloc out"))) {
       break;
     }
-    iota_kernel<<<(n + 255) / 256, 256, 0, st>>>(order, n);
+    // reads ordered by length, longest first
+    const uint32_t nb = ix->p.max_read_len + 1;
+    uint32_t* hist = nullptr;
+    if ((s = check_hip(hipMallocAsync((void**)&hist, sizeof(uint32_t) * nb, st), "alloc hist")))
+      break;
+    fill_u32_kernel<<<(nb + 255) / 256, 256, 0, st>>>(hist, 0u, nb);
+    len_hist_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, hist);
+    len_starts_kernel<<<1, 1024, 0, st>>>(hist, nb);
+    len_scatter_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, hist, order);
+    (void)hipFreeAsync(hist, st);
+    if ((s = check_hip(hipGetLastError(), "length sort"))) break;
     fill_u32_kernel<<<1, 64, 0, st>>>(ctr, 0u, 1u);
     ScanArgs a{};
     a.g2 = ix->g2; a.nmask = ix->nmask; a.Lpad = ix->Lpad;
     a.F = ix->F; a.NF = ix->NF; a.nseg = t.nseg;
-    a.prof = er.prof; a.mstride = er.mstride; a.lens = er.lens; a.order = order; a.n = n;
+    a.sel4 = er.sel4; a.cwg = er.mstride / 8; a.cw = t.cw; a.win_slots = t.win_slots;
+    a.xpool = xpool; a.dpool = (uint64_t)(M8 ^ X8);
+    a.lens = er.lens; a.order = order; a.n = n;
     a.R = t.R; a.ntiles = t.ntiles; a.C = t.C; a.nchunks = t.nchunks;
     a.total_work = t.ntiles * t.nchunks; a.work_ctr = ctr; a.partial = partial;
     a.nstrands = nstrands; a.mp_max = mp_max;
-    const size_t lds = lds_for(t.NP, mp_max);
+    const size_t lds = t.lds;
     if (t.NP == 8) s = launch_scan<8>(a, t.grid, lds, st);
     else if (t.NP == 16) s = launch_scan<16>(a, t.grid, lds, st);
     else s = launch_scan<32>(a, t.grid, lds, st);

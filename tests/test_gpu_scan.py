@@ -117,6 +117,8 @@ def _edge_case(G, F, lens, seed, M=1, X=-1, flags=0, n_runs=0, rate=0.15, max_le
     (30_000, 2064, [33, 100, 151]),                   # F not a multiple of 128
     (70_000, 4096, [36, 51, 100, 150, 250] * 4),      # mixed lengths, wide tiles
     (40_000, 1024, list(range(1, 130, 7))),           # ragged lengths across unroll
+    (30_000, 2048, list(range(1, 34)) + [95, 100, 111, 112, 113]),   # every m % 16
+    (40_000, 4096, list(range(1, 66, 2)) + [96, 127, 128, 129, 250]),  # m % 32, wide
 ])
 def test_edge_shapes(G, F, lens):
     got, ref = _edge_case(G, F, lens, seed=G % 997 + F)
