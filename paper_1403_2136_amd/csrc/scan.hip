@@ -105,15 +105,24 @@ __device__ inline uint32_t codes8(const uint32_t* __restrict__ lc, uint32_t k) {
   return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
 }
 
-// SUB Kadane steps (SUB <= 8) starting at read position k, with the window
+// LDS word x (uniform) of the window that starts at lane*NP: with one pad
+// word every NP words, its slot is lane*(NP+1) + x + x/NP (lane*NP is a
+// multiple of NP, so only the uniform part needs the division).
+template <int NP>
+__device__ inline uint32_t win_word(const uint32_t* __restrict__ lds, uint32_t lbase,
+                                    uint32_t x) {
+  return lds[lbase + (x + x / NP)];
+}
+
+// SUB Kadane steps (SUB <= 8) at read positions [k, k+SUB), with the window
 // loaded from LDS for exactly these steps.
 template <int NP, int SUB>
-__device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lb,
+__device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lbase,
                                   const uint32_t* __restrict__ lc, uint32_t k, uint64_t xpool,
                                   uint64_t dpool, s16x2 (&H)[NP], s16x2 (&B)[NP]) {
   uint32_t win[NP + SUB - 1];
 #pragma unroll
-  for (int i = 0; i < NP + SUB - 1; i++) win[i] = lds[phys<NP>(lb + k + i)];
+  for (int i = 0; i < NP + SUB - 1; i++) win[i] = win_word<NP>(lds, lbase, k + i);
   const uint32_t cc = codes8(lc, k);
 #pragma unroll
   for (int t = 0; t < SUB; t++) {
@@ -131,10 +140,10 @@ __device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lb,
 }
 
 // Kadane over one read strand of length m for this lane's NP offset pairs.
-// lc: the strand's 4-bit codes in LDS.  The first m % NP steps run as
-// unrolled sub-blocks of 8/4/2/1 steps, the rest as full NP-step blocks, so
-// no padding step is computed.  Returns the lane's per-pair maxima (biased by
-// -32768) in B.
+// lc: the strand's 4-bit codes in LDS.  Full NP-step blocks first (window in
+// registers, refilled from LDS one block ahead), then the last m % NP steps
+// as unrolled sub-blocks of 8/4/2/1 steps, so no padding step is computed.
+// Returns the lane's per-pair maxima (biased by -32768) in B.
 template <int NP>
 __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t lane,
                                     const uint32_t* __restrict__ lc, uint32_t m,
@@ -147,62 +156,65 @@ __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t l
     H[j] = lo;
     B[j] = lo;
   }
-  const uint32_t lb = lane * NP;
-  const uint32_t rem = m % NP;
-  uint32_t k = 0;
-  if (NP > 16 && (rem & 16)) {
-    kadane_sub<NP, 8>(lds, lb, lc, k, xpool, dpool, H, B);
-    kadane_sub<NP, 8>(lds, lb, lc, k + 8, xpool, dpool, H, B);
-    k += 16;
-  }
-  if (NP > 8 && (rem & 8)) { kadane_sub<NP, 8>(lds, lb, lc, k, xpool, dpool, H, B); k += 8; }
-  if (rem & 4) { kadane_sub<NP, 4>(lds, lb, lc, k, xpool, dpool, H, B); k += 4; }
-  if (rem & 2) { kadane_sub<NP, 2>(lds, lb, lc, k, xpool, dpool, H, B); k += 2; }
-  if (rem & 1) { kadane_sub<NP, 1>(lds, lb, lc, k, xpool, dpool, H, B); k += 1; }
-  if (k >= m) return;
-  // full blocks from k = rem; codes realigned by 4*(k%8) bits
-  const uint32_t csh = 4u * (k & 7u);
-  uint32_t win[2 * NP];
-  uint32_t nxt[NP];
-  uint32_t cn[CW + 1];
+  const uint32_t lbase = lane * (NP + 1);
+  const uint32_t mfull = m / NP * NP;
+  if (mfull) {
+    uint32_t win[2 * NP];
+    uint32_t nxt[NP];
+    uint32_t cn[CW];
 #pragma unroll
-  for (int i = 0; i < NP; i++) {
-    win[i] = lds[phys<NP>(lb + k + i)];
-    nxt[i] = lds[phys<NP>(lb + k + NP + i)];
-  }
-#pragma unroll
-  for (int i = 0; i <= CW; i++) cn[i] = __builtin_amdgcn_readfirstlane(lc[(k >> 3) + i]);
-  for (uint32_t kb = k; kb < m; kb += NP) {
-    uint32_t cc[CW];
-#pragma unroll
-    for (int i = 0; i < CW; i++)
-      cc[i] = (uint32_t)((((uint64_t)cn[i + 1] << 32) | cn[i]) >> csh);
-#pragma unroll
-    for (int i = 0; i < NP; i++) win[NP + i] = nxt[i];
-    // prefetch the next block's window words and code words (inside the
-    // staged ranges: the window covers lb + m + 2*NP words, the codes
-    // m/8 + NP/8 + 1 words)
-#pragma unroll
-    for (int i = 0; i < NP; i++) nxt[i] = lds[phys<NP>(lb + kb + 2 * NP + i)];
-#pragma unroll
-    for (int i = 0; i <= CW; i++)
-      cn[i] = __builtin_amdgcn_readfirstlane(lc[((kb + NP) >> 3) + i]);
-#pragma unroll
-    for (int t = 0; t < NP; t++) {
-      const uint32_t c = (cc[t >> 3] >> (4 * (t & 7))) & 15u;
-      const uint64_t pool = xpool ^ (dpool << (c << 3));
-      const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
-#pragma unroll
-      for (int j = 0; j < NP; j++) {
-        uint32_t sg = __builtin_amdgcn_perm(phi, plo, win[j + t]);
-        H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
-      }
-#pragma unroll
-      for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
+    for (int i = 0; i < NP; i++) {
+      win[i] = win_word<NP>(lds, lbase, i);
+      nxt[i] = win_word<NP>(lds, lbase, NP + i);
     }
 #pragma unroll
-    for (int i = 0; i < NP; i++) win[i] = win[NP + i];
+    for (int i = 0; i < CW; i++) cn[i] = __builtin_amdgcn_readfirstlane(lc[i]);
+    // pb = kb + kb/NP: slot offset of word kb; word kb + 2*NP + i (i < NP)
+    // sits at pb + 2*(NP+1) + i
+    uint32_t pb = 0;
+    for (uint32_t kb = 0; kb < mfull; kb += NP, pb += NP + 1) {
+      uint32_t cc[CW];
+#pragma unroll
+      for (int i = 0; i < CW; i++) cc[i] = cn[i];
+#pragma unroll
+      for (int i = 0; i < NP; i++) win[NP + i] = nxt[i];
+      // prefetch the next block's window words and code words (inside the
+      // staged ranges: the window covers lane*NP + m + 2*NP words, the codes
+      // m/8 + NP/8 + 1 words)
+      const uint32_t* lw = lds + lbase + pb + 2 * (NP + 1);
+#pragma unroll
+      for (int i = 0; i < NP; i++) nxt[i] = lw[i];
+#pragma unroll
+      for (int i = 0; i < CW; i++)
+        cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + NP) / 8 + i]);
+#pragma unroll
+      for (int t = 0; t < NP; t++) {
+        const uint32_t c = (cc[t >> 3] >> (4 * (t & 7))) & 15u;
+        const uint64_t pool = xpool ^ (dpool << (c << 3));
+        const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
+#pragma unroll
+        for (int j = 0; j < NP; j++) {
+          uint32_t sg = __builtin_amdgcn_perm(phi, plo, win[j + t]);
+          H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
+        }
+#pragma unroll
+        for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
+      }
+#pragma unroll
+      for (int i = 0; i < NP; i++) win[i] = win[NP + i];
+    }
   }
+  const uint32_t rem = m - mfull;
+  uint32_t k = mfull;
+  if (NP > 16 && (rem & 16)) {
+    kadane_sub<NP, 8>(lds, lbase, lc, k, xpool, dpool, H, B);
+    kadane_sub<NP, 8>(lds, lbase, lc, k + 8, xpool, dpool, H, B);
+    k += 16;
+  }
+  if (NP > 8 && (rem & 8)) { kadane_sub<NP, 8>(lds, lbase, lc, k, xpool, dpool, H, B); k += 8; }
+  if (rem & 4) { kadane_sub<NP, 4>(lds, lbase, lc, k, xpool, dpool, H, B); k += 4; }
+  if (rem & 2) { kadane_sub<NP, 2>(lds, lbase, lc, k, xpool, dpool, H, B); k += 2; }
+  if (rem & 1) kadane_sub<NP, 1>(lds, lbase, lc, k, xpool, dpool, H, B);
 }
 
 __device__ inline int wave_max_i32(int v) {
@@ -307,8 +319,17 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint32_t n) {
 // tiles, never a result.
 __global__ void len_hist_kernel(const uint32_t* __restrict__ lens, uint32_t n,
                                 uint32_t* __restrict__ hist) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&hist[lens[i]], 1u);
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t L = i < n ? lens[i] : 0xFFFFFFFFu;
+  // one atomic per distinct length in the wave
+  uint64_t todo = __ballot(i < n);
+  while (todo) {
+    const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
+    const uint32_t Ll = __shfl(L, lead, 64);
+    const uint64_t same = __ballot(L == Ll) & todo;
+    if ((threadIdx.x & 63) == lead) atomicAdd(&hist[Ll], (uint32_t)__builtin_popcountll(same));
+    todo &= ~same;
+  }
 }
 
 // hist[L] -> first output position of length L in descending-length order.
@@ -340,8 +361,23 @@ __global__ __launch_bounds__(1024) void len_starts_kernel(uint32_t* __restrict__
 
 __global__ void len_scatter_kernel(const uint32_t* __restrict__ lens, uint32_t n,
                                    uint32_t* __restrict__ starts, uint32_t* __restrict__ order) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) order[atomicAdd(&starts[lens[i]], 1u)] = i;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t L = i < n ? lens[i] : 0xFFFFFFFFu;
+  uint64_t todo = __ballot(i < n);
+  while (todo) {
+    const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
+    const uint32_t Ll = __shfl(L, lead, 64);
+    const uint64_t same = __ballot(L == Ll) & todo;
+    uint32_t base = 0;
+    if (lane == lead) base = atomicAdd(&starts[Ll], (uint32_t)__builtin_popcountll(same));
+    base = __shfl(base, lead, 64);
+    if ((same >> lane) & 1ull) {
+      const uint32_t rank = (uint32_t)__builtin_popcountll(same & ((1ull << lane) - 1ull));
+      order[base + rank] = i;
+    }
+    todo &= ~same;
+  }
 }
 
 // (score desc, fragment asc) order of candidates; negative fragment = none.
