@@ -169,6 +169,68 @@ maxss_status maxss_align_top(const maxss_index* index, const maxss_reads* reads,
                              const maxss_top2* top, uint32_t pad, maxss_aln* out,
                              char* cigar, uint64_t cigar_stride, void* stream);
 
+/* ---- Batching: reusable plans, HIP graphs, tile autotuning ---------------
+ * Not in the paper (which launches one grid per read); these serve mixed-
+ * length batches of device-resident reads with one persistent scan launch. */
+
+typedef struct maxss_plan maxss_plan; /* opaque, library-owned */
+
+/* A plan owns all scratch of one step (first phase + second phase) for up to
+ * `capacity` device-resident reads, with NW padding `pad` and CIGAR stride
+ * `cigar_stride` fixed.  Allocates device memory once, here.  A plan serves
+ * one stream at a time: calls that overlap on different streams race.
+ * Errors: EINVAL, ESTATE (index on another device), ENOMEM, EDEVICE. */
+maxss_status maxss_plan_create(const maxss_index* index, uint32_t capacity, uint32_t pad,
+                               uint64_t cigar_stride, maxss_plan** out);
+void maxss_plan_free(maxss_plan* plan);
+
+/* One step on device reads (reads->on_device must be 1, reads->n <=
+ * capacity): the same records maxss_scan_reads writes to `top` and, if `aln`
+ * and `cigar` are not NULL, those of maxss_align_top (with the plan's pad and
+ * stride).  No allocation and no host synchronisation: asynchronous on
+ * `stream`, and capturable into a HIP graph.  Errors: EINVAL, EDEVICE. */
+maxss_status maxss_plan_run(maxss_plan* plan, const maxss_reads* reads, maxss_top2* top,
+                            maxss_aln* aln, char* cigar, void* stream);
+
+/* maxss_plan_run recorded once into a HIP graph and replayed: the first call,
+ * or a call whose buffers, read count or stream differ from the recorded
+ * ones, captures the step on `stream` (must not be NULL); later calls replay
+ * it (new buffer contents are fine).  Errors: as maxss_plan_run. */
+maxss_status maxss_plan_run_graph(maxss_plan* plan, const maxss_reads* reads, maxss_top2* top,
+                                  maxss_aln* aln, char* cigar, void* stream);
+
+/* Autotuner result: the tile shape chosen (np = offset pairs per lane,
+ * reads_per_tile, rounds = work items per resident wave; 0 = built-in), the
+ * timed scan of the sample with it and with the built-in shape, how many
+ * candidates were tried, how many were rejected because a record differed
+ * from the built-in shape's (never chosen), and whether it came from the
+ * cache file. */
+typedef struct {
+  int32_t np;
+  uint32_t reads_per_tile;
+  uint32_t rounds;
+  float best_ms;
+  float default_ms;
+  uint32_t tried;
+  uint32_t rejected;
+  uint32_t from_cache;
+} maxss_tune_result;
+
+/* Time candidate tile shapes of the scan on `sample` (host or device reads)
+ * and set the fastest one whose records are byte-identical to the built-in
+ * shape's on the index (used by every later scan on it).  With cache_path
+ * (may be NULL), a matching entry (device architecture, fragment geometry,
+ * read-length and batch-size bucket) is reused without timing, and a new
+ * result is appended.  Must not run concurrently with scans on the index.
+ * Errors: EINVAL, ETOOLONG (host sample), ENOMEM, EDEVICE. */
+maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sample, const char* cache_path,
+                            maxss_tune_result* result);
+
+/* Force a tile shape (np 0/8/16/32, reads_per_tile 0..64, rounds 0..1024;
+ * 0 = built-in).  Results never depend on it.  Errors: EINVAL. */
+maxss_status maxss_index_set_tiles(maxss_index* index, int32_t np, uint32_t reads_per_tile,
+                                   uint32_t rounds);
+
 /* Kernel timing for measurement.  maxss_profile_enable(1) clears the records
  * and brackets every later launch of the library's kernels with HIP events on
  * the launch stream; maxss_profile_enable(0) stops recording.

@@ -49,6 +49,13 @@ class Params(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("np", ctypes.c_int32), ("reads_per_tile", ctypes.c_uint32),
+                ("rounds", ctypes.c_uint32), ("best_ms", ctypes.c_float),
+                ("default_ms", ctypes.c_float), ("tried", ctypes.c_uint32),
+                ("rejected", ctypes.c_uint32), ("from_cache", ctypes.c_uint32)]
+
+
 class Reads(ctypes.Structure):
     _fields_ = [("seq", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_uint32),
                 ("on_device", ctypes.c_uint32)]
@@ -56,8 +63,9 @@ class Reads(ctypes.Structure):
 
 # every function declared in include/maxss.h
 EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_scan_reads",
-           "maxss_align_top", "maxss_profile_enable", "maxss_profile_read", "maxss_last_error",
-           "maxss_version")
+           "maxss_align_top", "maxss_plan_create", "maxss_plan_free", "maxss_plan_run",
+           "maxss_plan_run_graph", "maxss_autotune", "maxss_index_set_tiles",
+           "maxss_profile_enable", "maxss_profile_read", "maxss_last_error", "maxss_version")
 
 _lib = None
 
@@ -88,6 +96,20 @@ def lib():
         L.maxss_align_top.restype = c.c_int
         L.maxss_align_top.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p, c.c_uint32,
                                       c.c_void_p, c.c_void_p, c.c_uint64, c.c_void_p]
+        L.maxss_plan_create.restype = c.c_int
+        L.maxss_plan_create.argtypes = [c.c_void_p, c.c_uint32, c.c_uint32, c.c_uint64,
+                                        c.POINTER(c.c_void_p)]
+        L.maxss_plan_free.restype = None
+        L.maxss_plan_free.argtypes = [c.c_void_p]
+        for fn in (L.maxss_plan_run, L.maxss_plan_run_graph):
+            fn.restype = c.c_int
+            fn.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p, c.c_void_p, c.c_void_p,
+                           c.c_void_p]
+        L.maxss_autotune.restype = c.c_int
+        L.maxss_autotune.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_char_p,
+                                     c.POINTER(TuneResult)]
+        L.maxss_index_set_tiles.restype = c.c_int
+        L.maxss_index_set_tiles.argtypes = [c.c_void_p, c.c_int32, c.c_uint32, c.c_uint32]
         L.maxss_profile_enable.restype = c.c_int
         L.maxss_profile_enable.argtypes = [c.c_int]
         L.maxss_profile_read.restype = c.c_int
@@ -220,6 +242,46 @@ def maxss_align_top(handle: int, seq, offsets, top, pad: int = 100, cigar_stride
     return res, cigars
 
 
+def maxss_plan_create(handle, capacity: int, pad: int = 100, cigar_stride: int = 256) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().maxss_plan_create(h_(handle), capacity, pad, cigar_stride, ctypes.byref(h)))
+    return h.value
+
+
+def maxss_plan_free(plan: int) -> None:
+    lib().maxss_plan_free(plan)
+
+
+def maxss_plan_run(plan: int, seq, offsets, top, aln=None, cigar=None, stream=None,
+                   graph: bool = False):
+    """One step on device reads (torch tensors); `graph` replays a captured
+    HIP graph (needs a non-default stream)."""
+    r = _reads_struct(seq, offsets, True)
+    fn = lib().maxss_plan_run_graph if graph else lib().maxss_plan_run
+    _check(fn(plan, ctypes.byref(r), _ptr(top), _ptr(aln), _ptr(cigar), _stream_handle(stream)))
+
+
+def maxss_autotune(handle, seq, offsets, cache_path: str | None = None) -> dict:
+    """Tune the index's tile shape on a sample (host arrays or device tensors)."""
+    res = TuneResult()
+    if hasattr(seq, "is_cuda") and seq.is_cuda:
+        r = _reads_struct(seq, offsets, True)
+        keep = None
+    else:
+        s = _as_u8(seq)
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        r = Reads(s.ctypes.data, off.ctypes.data, off.size - 1, 0)
+        keep = (s, off)
+    _check(lib().maxss_autotune(h_(handle), ctypes.byref(r),
+                                cache_path.encode() if cache_path else None, ctypes.byref(res)))
+    del keep
+    return {f: getattr(res, f) for f, _ in TuneResult._fields_}
+
+
+def maxss_index_set_tiles(handle, np_: int = 0, reads_per_tile: int = 0, rounds: int = 0) -> None:
+    _check(lib().maxss_index_set_tiles(h_(handle), np_, reads_per_tile, rounds))
+
+
 def decode_cigar(buf: np.ndarray, i: int, stride: int) -> str:
     row = buf[i * stride:(i + 1) * stride]
     z = np.nonzero(row == 0)[0]
@@ -231,6 +293,29 @@ def h_(handle):
     if isinstance(handle, Index):
         return handle.handle
     return handle
+
+
+class Plan:
+    """Owner of a launch plan (all scratch of a step, preallocated)."""
+
+    def __init__(self, index: "Index", capacity: int, pad: int = 100, cigar_stride: int = 256):
+        self.index = index
+        self.handle = maxss_plan_create(index.handle, capacity, pad, cigar_stride)
+        self.capacity, self.pad, self.cigar_stride = capacity, pad, cigar_stride
+
+    def run(self, seq, offsets, top, aln=None, cigar=None, stream=None, graph=False):
+        maxss_plan_run(self.handle, seq, offsets, top, aln, cigar, stream, graph)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            maxss_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Index:
@@ -251,6 +336,12 @@ class Index:
               cigar=None, stream=None):
         return maxss_align_top(self.handle, seq, offsets, top, pad, cigar_stride, out, cigar,
                                stream)
+
+    def set_tiles(self, np_: int = 0, reads_per_tile: int = 0, rounds: int = 0):
+        maxss_index_set_tiles(self.handle, np_, reads_per_tile, rounds)
+
+    def autotune(self, seq, offsets, cache_path=None):
+        return maxss_autotune(self.handle, seq, offsets, cache_path)
 
     def close(self):
         if getattr(self, "handle", None):

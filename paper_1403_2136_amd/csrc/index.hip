@@ -115,8 +115,14 @@ static std::mutex g_prof_mu;
 static std::vector<ProfRec> g_prof;
 static std::atomic<int> g_prof_on{0};
 
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+
 ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
-  if (!g_prof_on.load()) return;
+  if (!g_prof_on.load() || stream_capturing(st)) return;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     a = b = nullptr;
     return;
@@ -192,25 +198,28 @@ __global__ __launch_bounds__(256) void encode_reads_kernel(
 
 static constexpr uint32_t kSlack = 64;
 
-maxss_status encode_reads(const Index* ix, const DeviceReads& r, hipStream_t st,
-                          EncodedReads* e) {
+maxss_status alloc_encoded(const Index* ix, uint32_t n, hipStream_t st, EncodedReads* e) {
   e->mstride = read_stride(ix);
-  uint64_t n = r.n;
   maxss_status s;
   if ((s = check_hip(hipMallocAsync((void**)&e->sel4,
-                                    sizeof(uint32_t) * (n * 2 * (e->mstride / 8) + kSlack), st),
+                                    sizeof(uint32_t) * ((uint64_t)n * 2 * (e->mstride / 8) + kSlack),
+                                    st),
                      "hipMallocAsync(read codes)")))
     return s;
-  if ((s = check_hip(hipMallocAsync((void**)&e->codes, n * e->mstride + kSlack, st),
+  if ((s = check_hip(hipMallocAsync((void**)&e->codes, (uint64_t)n * e->mstride + kSlack, st),
                      "hipMallocAsync(read bases)")))
     return s;
-  if ((s = check_hip(hipMallocAsync((void**)&e->lens, sizeof(uint32_t) * (n + 1), st),
-                     "hipMallocAsync(lens)")))
-    return s;
-  uint32_t blocks = (uint32_t)((n * 64 + 255) / 256);
+  return check_hip(hipMallocAsync((void**)&e->lens, sizeof(uint32_t) * ((uint64_t)n + 1), st),
+                   "hipMallocAsync(lens)");
+}
+
+maxss_status encode_reads_into(const Index* ix, const DeviceReads& r, hipStream_t st,
+                               const EncodedReads& e) {
+  const uint64_t n = r.n;
+  const uint32_t blocks = (uint32_t)((n * 64 + 255) / 256);
   ProfScope prof("encode", st);
-  encode_reads_kernel<<<blocks, 256, 0, st>>>(r.seq, r.off, r.n, ix->p.max_read_len,
-                                              e->mstride, e->sel4, e->codes, e->lens);
+  encode_reads_kernel<<<blocks, 256, 0, st>>>(r.seq, r.off, r.n, ix->p.max_read_len, e.mstride,
+                                              e.sel4, e.codes, e.lens);
   return check_hip(hipGetLastError(), "encode_reads_kernel");
 }
 

@@ -20,9 +20,17 @@ enum : uint8_t { kA = 0, kC = 1, kG = 2, kT = 3, kN = 4 };
 //           exact re-scan of the two winning fragments.
 // All three cover positions [0, Lpad); positions >= G are N.  Lpad leaves room
 // for the longest window of the last fragment plus every tile's staging tail.
+// Tile shape forced by the autotuner (0 fields = the built-in choice).
+struct TileOverride {
+  int NP = 0;            // packed offset pairs per lane: 8, 16 or 32
+  uint32_t R = 0;        // reads per tile
+  uint32_t rounds = 0;   // minimum rounds of work items per resident wave
+};
+
 struct Index {
   int device = 0;
   int num_cu = 0;
+  TileOverride tune;     // set only by maxss_autotune
   uint64_t G = 0;
   uint32_t F = 0, NF = 0;
   maxss_params p{};
@@ -76,12 +84,51 @@ struct EncodedReads {
   uint32_t mstride = 0;
 };
 
-maxss_status encode_reads(const Index* ix, const DeviceReads& r, hipStream_t st,
-                          EncodedReads* out);
+// Allocation (stream-ordered) and release of encoded reads for n reads.
+maxss_status alloc_encoded(const Index* ix, uint32_t n, hipStream_t st, EncodedReads* e);
 void release_encoded(EncodedReads* e, hipStream_t st);
+// Encode n device reads into preallocated buffers (no allocation).
+maxss_status encode_reads_into(const Index* ix, const DeviceReads& r, hipStream_t st,
+                               const EncodedReads& e);
+
+// Scratch of the first phase for up to `cap` reads (library-allocated).
+struct ScanWork {
+  EncodedReads er;
+  uint32_t* order = nullptr;   // [cap]
+  uint32_t* hist = nullptr;    // [max_read_len + 1]
+  uint32_t* ctr = nullptr;     // [1]
+  int4* partial = nullptr;     // [partial_cap]
+  uint64_t partial_cap = 0;    // entries (read x fragment chunk)
+};
+
+// Entries the partial buffer needs for n reads (built-in or forced tiles).
+uint64_t scan_partial_entries(const Index* ix, uint32_t n, const TileOverride* force);
+maxss_status alloc_scan_work(const Index* ix, uint32_t n, uint64_t partial_cap, bool stream_ordered,
+                             hipStream_t st, ScanWork* w);
+void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st);
+
+// First phase on n device reads with the given scratch: encode, length sort,
+// scan, merge, exact re-scan of the winners.  No allocation, no host sync, so
+// it may be captured into a graph.  `force` (may be NULL) overrides tiles.
+maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* dout,
+                           const ScanWork& w, const TileOverride* force, hipStream_t st);
+
+// Second phase scratch and launch (reads already encoded in `er`).
+struct NwShape {
+  uint32_t cw = 0, ncols_max = 0, rowbytes = 0, grid = 0;
+  size_t lds = 0;
+};
+maxss_status nw_shape(const Index* ix, uint32_t n, uint32_t pad, NwShape* sh);
+maxss_status nw_pipeline(const Index* ix, const EncodedReads& er, uint32_t n,
+                         const maxss_top2* dtop, uint32_t pad, maxss_aln* dout, char* dcig,
+                         uint64_t cigar_stride, uint8_t* slab, const NwShape& sh,
+                         hipStream_t st);
 
 // Event bracket of one kernel launch when profiling is on (see
 // maxss_profile_enable); a no-op otherwise.
+// True while `st` is being captured into a graph.
+bool stream_capturing(hipStream_t st);
+
 struct ProfScope {
   ProfScope(const char* name, hipStream_t st);
   ~ProfScope();

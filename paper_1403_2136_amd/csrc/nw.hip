@@ -233,6 +233,55 @@ __global__ __launch_bounds__(kNwThreads) void nw_kernel(NwArgs a) {
   }
 }
 
+maxss_status nw_shape(const Index* ix, uint32_t n, uint32_t pad, NwShape* sh) {
+  const uint32_t m_max = ix->p.max_read_len;
+  const uint64_t ncols_need = (uint64_t)ix->F + m_max - 1 + 2ull * pad;
+  uint32_t cw = (uint32_t)((ncols_need + kNwThreads - 1) / kNwThreads);
+  cw = (cw + 3) & ~3u;
+  sh->cw = cw;
+  sh->ncols_max = cw * kNwThreads;
+  sh->rowbytes = sh->ncols_max / 4;
+  sh->lds = (size_t)2 * (sh->ncols_max + 1) * 4 + m_max + sh->ncols_max + (m_max + sh->ncols_max) + 16;
+  if (sh->lds > 160 * 1024)
+    return fail(MAXSS_EINVAL, "NW region too wide for LDS (%zu bytes)", sh->lds);
+  maxss_status s;
+  if (sh->lds > 65536 &&
+      (s = check_hip(hipFuncSetAttribute((const void*)nw_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh->lds),
+                     "hipFuncSetAttribute(nw_kernel)")))
+    return s;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nw_kernel, kNwThreads, sh->lds) !=
+          hipSuccess ||
+      occ < 1)
+    occ = 1;
+  uint32_t grid = (uint32_t)ix->num_cu * (uint32_t)occ;
+  if (n && grid > n) grid = n;
+  sh->grid = grid ? grid : 1;
+  return MAXSS_OK;
+}
+
+maxss_status nw_pipeline(const Index* ix, const EncodedReads& er, uint32_t n,
+                         const maxss_top2* dtop, uint32_t pad, maxss_aln* dout, char* dcig,
+                         uint64_t cigar_stride, uint8_t* slab, const NwShape& sh,
+                         hipStream_t st) {
+  if (n == 0) return MAXSS_OK;
+  NwArgs a{};
+  a.gcodes = ix->codes; a.G = ix->G; a.F = ix->F; a.NF = ix->NF;
+  a.rcodes = er.codes; a.lens = er.lens; a.mstride = er.mstride;
+  a.top = dtop; a.n = n; a.pad = pad;
+  a.M = ix->p.match; a.X = ix->p.mismatch; a.gap = ix->p.gap;
+  a.global_mode = (ix->p.flags & MAXSS_NW_GLOBAL) ? 1 : 0;
+  a.cw = sh.cw; a.rowbytes = sh.rowbytes; a.slab = slab; a.m_max = ix->p.max_read_len;
+  a.out = dout; a.cigar = dcig; a.cigar_stride = cigar_stride;
+  const uint32_t grid = sh.grid < n ? sh.grid : n;
+  {
+    ProfScope prof("nw", st);
+    nw_kernel<<<grid, kNwThreads, sh.lds, st>>>(a);
+  }
+  return check_hip(hipGetLastError(), "nw_kernel");
+}
+
 }  // namespace maxss
 
 using namespace maxss;
@@ -262,32 +311,15 @@ extern "C" maxss_status maxss_align_top(const maxss_index* index, const maxss_re
   maxss_aln* dout = nullptr;
   char* dcig = nullptr;
   do {
+    NwShape sh;
+    if ((s = nw_shape(ix, n, pad, &sh))) break;
     if ((s = stage_reads(reads, st, &dr))) break;
-    if ((s = encode_reads(ix, dr, st, &er))) break;
-    const uint32_t m_max = ix->p.max_read_len;
-    const uint64_t ncols_need = (uint64_t)ix->F + m_max - 1 + 2ull * pad;
-    uint32_t cw = (uint32_t)((ncols_need + kNwThreads - 1) / kNwThreads);
-    cw = (cw + 3) & ~3u;
-    const uint32_t ncols_max = cw * kNwThreads;
-    const uint32_t rowbytes = ncols_max / 4;
-    const size_t lds = (size_t)2 * (ncols_max + 1) * 4 + m_max + ncols_max + (m_max + ncols_max) + 16;
-    if (lds > 160 * 1024)
-      { s = fail(MAXSS_EINVAL, "NW region too wide for LDS (%zu bytes)", lds); break; }
-    if (lds > 65536 &&
-        (s = check_hip(hipFuncSetAttribute((const void*)nw_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                       "hipFuncSetAttribute(nw_kernel)")))
-      break;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, nw_kernel, kNwThreads, lds) != hipSuccess ||
-        occ < 1)
-      occ = 1;
-    uint32_t grid = (uint32_t)ix->num_cu * (uint32_t)occ;
-    if (grid > n) grid = n;
-    if ((s = check_hip(hipMallocAsync((void**)&slab, (size_t)grid * m_max * rowbytes, st),
+    if ((s = alloc_encoded(ix, n, st, &er))) break;
+    if ((s = encode_reads_into(ix, dr, st, er))) break;
+    if ((s = check_hip(hipMallocAsync((void**)&slab, (size_t)sh.grid * ix->p.max_read_len * sh.rowbytes,
+                                      st),
                        "alloc NW slab")))
       break;
-    NwArgs a{};
     if (reads->on_device) {
       dtop = const_cast<maxss_top2*>(top);
       dout = out;
@@ -300,18 +332,7 @@ extern "C" maxss_status maxss_align_top(const maxss_index* index, const maxss_re
                          "copy top")))
         break;
     }
-    a.gcodes = ix->codes; a.G = ix->G; a.F = ix->F; a.NF = ix->NF;
-    a.rcodes = er.codes; a.lens = er.lens; a.mstride = er.mstride;
-    a.top = dtop; a.n = n; a.pad = pad;
-    a.M = ix->p.match; a.X = ix->p.mismatch; a.gap = ix->p.gap;
-    a.global_mode = (ix->p.flags & MAXSS_NW_GLOBAL) ? 1 : 0;
-    a.cw = cw; a.rowbytes = rowbytes; a.slab = slab; a.m_max = m_max;
-    a.out = dout; a.cigar = dcig; a.cigar_stride = cigar_stride;
-    {
-      ProfScope prof("nw", st);
-      nw_kernel<<<grid, kNwThreads, lds, st>>>(a);
-    }
-    if ((s = check_hip(hipGetLastError(), "nw_kernel"))) break;
+    if ((s = nw_pipeline(ix, er, n, dtop, pad, dout, dcig, cigar_stride, slab, sh, st))) break;
     if (!reads->on_device) {
       if ((s = check_hip(hipMemcpyAsync(out, dout, sizeof(maxss_aln) * n, hipMemcpyDeviceToHost, st),
                          "copy aln")) ||

@@ -1,0 +1,352 @@
+// Batching: reusable launch plans (no allocation per call), HIP graph capture
+// and replay of a whole step, and the tile autotuner (HIP, gfx950).
+//
+// A plan owns every scratch buffer of the first and second phase for up to
+// `capacity` device-resident reads, so one step -- encode, length sort, the
+// persistent scan, merge, re-scan of the winners, NW -- is a fixed sequence
+// of kernel launches on one stream with no allocation and no host
+// synchronisation.  That sequence is captured once into a HIP graph and
+// replayed for every batch of the same shape (same buffers, same read count);
+// reads of uneven lengths share the one persistent scan launch.
+//
+// The autotuner times candidate tile shapes (offset pairs per lane, reads per
+// tile, rounds of work items per wave) on a sample of reads and keeps the
+// fastest whose records are byte-identical to the built-in shape's: tiles
+// change only the order of an exact integer computation, never a result.
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace maxss {
+
+struct Plan {
+  const Index* ix = nullptr;
+  uint32_t capacity = 0, pad = 0;
+  uint64_t cigar_stride = 0;
+  ScanWork w;
+  NwShape nsh;
+  uint8_t* slab = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // what the captured graph was recorded for
+  const void* k_seq = nullptr;
+  const void* k_off = nullptr;
+  uint32_t k_n = 0;
+  void *k_top = nullptr, *k_aln = nullptr, *k_cig = nullptr;
+  hipStream_t k_st = nullptr;
+};
+
+static void drop_graph(Plan* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+}
+
+static maxss_status check_run_args(Plan* p, const maxss_reads* r, maxss_top2* top, maxss_aln* aln,
+                                   char* cig) {
+  if (!p || !r || !top) return fail(MAXSS_EINVAL, "NULL argument");
+  if (!r->on_device) return fail(MAXSS_EINVAL, "plans take device-resident reads only");
+  if (r->n > p->capacity) return fail(MAXSS_EINVAL, "%u reads exceed the plan capacity %u", r->n,
+                                      p->capacity);
+  if (r->n && (!r->seq || !r->offsets)) return fail(MAXSS_EINVAL, "NULL reads");
+  if ((aln == nullptr) != (cig == nullptr)) return fail(MAXSS_EINVAL, "aln and cigar go together");
+  return MAXSS_OK;
+}
+
+static maxss_status plan_step(Plan* p, const maxss_reads* r, maxss_top2* top, maxss_aln* aln,
+                              char* cig, hipStream_t st) {
+  DeviceReads dr;
+  dr.seq = r->seq;
+  dr.off = r->offsets;
+  dr.n = r->n;
+  maxss_status s = scan_pipeline(p->ix, dr, top, p->w, nullptr, st);
+  if (s || !aln) return s;
+  return nw_pipeline(p->ix, p->w.er, r->n, top, p->pad, aln, cig, p->cigar_stride, p->slab,
+                     p->nsh, st);
+}
+
+// (NP, R, rounds) candidates the autotuner tries for an index.
+static std::vector<TileOverride> tile_candidates(const Index* ix) {
+  std::vector<TileOverride> c;
+  const int nps[3] = {8, 16, 32};
+  const uint32_t rs[3] = {8, 16, 32};
+  const uint32_t rounds[3] = {4, 8, 16};
+  for (int np : nps) {
+    if (128u * (uint32_t)np > (ix->F > 1024u ? ix->F : 1024u)) continue;  // mostly idle lanes
+    for (uint32_t R : rs)
+      for (uint32_t rd : rounds) c.push_back(TileOverride{np, R, rd});
+  }
+  return c;
+}
+
+}  // namespace maxss
+
+using namespace maxss;
+
+extern "C" maxss_status maxss_plan_create(const maxss_index* index, uint32_t capacity, uint32_t pad,
+                                          uint64_t cigar_stride, maxss_plan** out) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  if (!ix || !out) return fail(MAXSS_EINVAL, "NULL argument");
+  if (capacity == 0) return fail(MAXSS_EINVAL, "capacity must be > 0");
+  if (cigar_stride < 2) return fail(MAXSS_EINVAL, "cigar_stride must be >= 2");
+  if (pad > (1u << 20)) return fail(MAXSS_EINVAL, "pad %u too large", pad);
+  int cur = 0;
+  maxss_status s;
+  if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;
+  if (cur != ix->device) return fail(MAXSS_ESTATE, "index lives on device %d, current is %d",
+                                     ix->device, cur);
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return fail(MAXSS_ENOMEM, "host allocation");
+  p->ix = ix;
+  p->capacity = capacity;
+  p->pad = pad;
+  p->cigar_stride = cigar_stride;
+  // the chunk buffer must serve any batch size up to capacity, and any
+  // shape the autotuner may later pick
+  uint64_t cap = 0;
+  const TileOverride none{};
+  for (uint32_t n = capacity;; n = (n + 1) / 2) {
+    for (const TileOverride* f : {(const TileOverride*)nullptr, &none}) {
+      const uint64_t e = scan_partial_entries(ix, n, f);
+      cap = e > cap ? e : cap;
+    }
+    for (const TileOverride& t : tile_candidates(ix)) {
+      const uint64_t e = scan_partial_entries(ix, n, &t);
+      cap = e > cap ? e : cap;
+    }
+    if (n == 1) break;
+  }
+  do {
+    if ((s = alloc_scan_work(ix, capacity, cap, false, nullptr, &p->w))) break;
+    if ((s = nw_shape(ix, capacity, pad, &p->nsh))) break;
+    if ((s = check_hip(hipMalloc((void**)&p->slab,
+                                 (size_t)p->nsh.grid * ix->p.max_read_len * p->nsh.rowbytes),
+                       "alloc NW slab")))
+      break;
+  } while (0);
+  if (s) {
+    maxss_plan_free(reinterpret_cast<maxss_plan*>(p));
+    return s;
+  }
+  *out = reinterpret_cast<maxss_plan*>(p);
+  return MAXSS_OK;
+}
+
+extern "C" void maxss_plan_free(maxss_plan* plan) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return;
+  drop_graph(p);
+  release_scan_work(&p->w, false, nullptr);
+  if (p->slab) (void)hipFree(p->slab);
+  delete p;
+}
+
+extern "C" maxss_status maxss_plan_run(maxss_plan* plan, const maxss_reads* reads,
+                                       maxss_top2* top, maxss_aln* aln, char* cigar,
+                                       void* stream) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  maxss_status s;
+  if ((s = check_run_args(p, reads, top, aln, cigar))) return s;
+  if (reads->n == 0) return MAXSS_OK;
+  return plan_step(p, reads, top, aln, cigar, (hipStream_t)stream);
+}
+
+extern "C" maxss_status maxss_plan_run_graph(maxss_plan* plan, const maxss_reads* reads,
+                                             maxss_top2* top, maxss_aln* aln, char* cigar,
+                                             void* stream) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  maxss_status s;
+  if ((s = check_run_args(p, reads, top, aln, cigar))) return s;
+  if (!stream) return fail(MAXSS_EINVAL, "graph capture needs a non-default stream");
+  if (reads->n == 0) return MAXSS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const bool same = p->exec && p->k_seq == reads->seq && p->k_off == reads->offsets &&
+                    p->k_n == reads->n && p->k_top == top && p->k_aln == aln &&
+                    p->k_cig == cigar && p->k_st == st;
+  if (!same) {
+    drop_graph(p);
+    if ((s = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal),
+                       "hipStreamBeginCapture")))
+      return s;
+    maxss_status rs = plan_step(p, reads, top, aln, cigar, st);
+    hipGraph_t g = nullptr;
+    s = check_hip(hipStreamEndCapture(st, &g), "hipStreamEndCapture");
+    if (rs || s) {
+      if (g) (void)hipGraphDestroy(g);
+      return rs ? rs : s;
+    }
+    p->graph = g;
+    if ((s = check_hip(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0),
+                       "hipGraphInstantiate"))) {
+      drop_graph(p);
+      return s;
+    }
+    p->k_seq = reads->seq;
+    p->k_off = reads->offsets;
+    p->k_n = reads->n;
+    p->k_top = top;
+    p->k_aln = aln;
+    p->k_cig = cigar;
+    p->k_st = st;
+  }
+  return check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");
+}
+
+extern "C" maxss_status maxss_index_set_tiles(maxss_index* index, int32_t np,
+                                              uint32_t reads_per_tile, uint32_t rounds) {
+  clear_error();
+  Index* ix = reinterpret_cast<Index*>(index);
+  if (!ix) return fail(MAXSS_EINVAL, "NULL index");
+  if (np != 0 && np != 8 && np != 16 && np != 32)
+    return fail(MAXSS_EINVAL, "np must be 0, 8, 16 or 32 (got %d)", np);
+  if (reads_per_tile > 64) return fail(MAXSS_EINVAL, "reads_per_tile must be <= 64");
+  if (rounds > 1024) return fail(MAXSS_EINVAL, "rounds must be <= 1024");
+  ix->tune = TileOverride{np, reads_per_tile, rounds};
+  return MAXSS_OK;
+}
+
+// Cache key of a tuning result: architecture, fragment geometry, read-length
+// bucket and batch-size bucket.
+static std::string tune_key(const Index* ix, uint32_t n) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, ix->device);
+  uint32_t nb = 1;
+  while (nb < n) nb <<= 1;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s F=%u NF=%u mstride=%u nbucket=%u strands=%u", prop.gcnArchName,
+           ix->F, ix->NF, read_stride(ix), nb, (ix->p.flags & MAXSS_ONE_STRAND) ? 1u : 2u);
+  return std::string(buf);
+}
+
+extern "C" maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sample,
+                                       const char* cache_path, maxss_tune_result* result) {
+  clear_error();
+  Index* ix = reinterpret_cast<Index*>(index);
+  if (!ix || !sample || !result) return fail(MAXSS_EINVAL, "NULL argument");
+  if (sample->n == 0) return fail(MAXSS_EINVAL, "empty sample");
+  maxss_status s;
+  if (!sample->on_device && (s = validate_host_reads(ix, sample))) return s;
+  int cur = 0;
+  if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;
+  if (cur != ix->device) return fail(MAXSS_ESTATE, "index lives on device %d, current is %d",
+                                     ix->device, cur);
+  memset(result, 0, sizeof(*result));
+  const std::string key = tune_key(ix, sample->n);
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (fgets(line, sizeof line, f)) {
+        int np = 0;
+        unsigned R = 0, rd = 0;
+        float best = 0, def = 0;
+        const char* bar = strchr(line, '|');
+        if (!bar || std::string(line, bar - line) != key) continue;
+        if (sscanf(bar + 1, " np=%d R=%u rounds=%u best_ms=%f default_ms=%f", &np, &R, &rd, &best,
+                   &def) == 5) {
+          ix->tune = TileOverride{np, R, rd};
+          result->np = np;
+          result->reads_per_tile = R;
+          result->rounds = rd;
+          result->best_ms = best;
+          result->default_ms = def;
+          result->from_cache = 1;
+        }
+      }
+      fclose(f);
+      if (result->from_cache) return MAXSS_OK;
+    }
+  }
+  hipStream_t st = nullptr;
+  DeviceReads dr;
+  ScanWork w;
+  maxss_top2 *ref = nullptr, *got = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const uint32_t n = sample->n;
+  std::vector<maxss_top2> h_ref(n), h_got(n);
+  const std::vector<TileOverride> cands = tile_candidates(ix);
+  const TileOverride none{};
+  do {
+    if ((s = check_hip(hipStreamCreate(&st), "hipStreamCreate"))) break;
+    if ((s = check_hip(hipEventCreate(&e0), "hipEventCreate")) ||
+        (s = check_hip(hipEventCreate(&e1), "hipEventCreate")))
+      break;
+    if ((s = stage_reads(sample, st, &dr))) break;
+    uint64_t cap = scan_partial_entries(ix, n, &none);
+    for (const TileOverride& t : cands) {
+      const uint64_t e = scan_partial_entries(ix, n, &t);
+      cap = e > cap ? e : cap;
+    }
+    if ((s = alloc_scan_work(ix, n, cap, false, st, &w))) break;
+    if ((s = check_hip(hipMalloc((void**)&ref, sizeof(maxss_top2) * n), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&got, sizeof(maxss_top2) * n), "alloc")))
+      break;
+    auto timed = [&](const TileOverride* f, maxss_top2* out, float* ms) -> maxss_status {
+      maxss_status q;
+      if ((q = scan_pipeline(ix, dr, out, w, f, st))) return q;  // warm-up
+      if ((q = check_hip(hipEventRecord(e0, st), "hipEventRecord"))) return q;
+      if ((q = scan_pipeline(ix, dr, out, w, f, st))) return q;
+      if ((q = check_hip(hipEventRecord(e1, st), "hipEventRecord"))) return q;
+      if ((q = check_hip(hipEventSynchronize(e1), "hipEventSynchronize"))) return q;
+      return check_hip(hipEventElapsedTime(ms, e0, e1), "hipEventElapsedTime");
+    };
+    float def_ms = 0;
+    if ((s = timed(&none, ref, &def_ms))) break;
+    if ((s = check_hip(hipMemcpy(h_ref.data(), ref, sizeof(maxss_top2) * n, hipMemcpyDeviceToHost),
+                       "copy")))
+      break;
+    TileOverride best = none;
+    float best_ms = def_ms;
+    for (const TileOverride& t : cands) {
+      float ms = 0;
+      if ((s = timed(&t, got, &ms))) break;
+      if ((s = check_hip(hipMemcpy(h_got.data(), got, sizeof(maxss_top2) * n, hipMemcpyDeviceToHost),
+                         "copy")))
+        break;
+      result->tried++;
+      if (memcmp(h_got.data(), h_ref.data(), sizeof(maxss_top2) * n) != 0) {
+        result->rejected++;  // a shape that changes a record is never chosen
+        continue;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+    if (s) break;
+    ix->tune = best;
+    result->np = best.NP;
+    result->reads_per_tile = best.R;
+    result->rounds = best.rounds;
+    result->best_ms = best_ms;
+    result->default_ms = def_ms;
+    if (cache_path) {
+      FILE* f = fopen(cache_path, "a");
+      if (f) {
+        fprintf(f, "%s| np=%d R=%u rounds=%u best_ms=%.4f default_ms=%.4f\n", key.c_str(), best.NP,
+                best.R, best.rounds, best_ms, def_ms);
+        fclose(f);
+      }
+    }
+  } while (0);
+  if (ref) (void)hipFree(ref);
+  if (got) (void)hipFree(got);
+  if (st) (void)hipStreamSynchronize(st);
+  release_scan_work(&w, false, st);
+  release_reads(&dr, st);
+  if (st) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return s;
+}

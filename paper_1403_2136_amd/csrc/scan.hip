@@ -35,6 +35,9 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "internal.h"
 
@@ -497,7 +500,14 @@ static maxss_status launch_scan(const ScanArgs& a, uint32_t grid, size_t lds, hi
   return check_hip(hipGetLastError(), "scan_kernel");
 }
 
+// Resident scan waves per CU for (NP, LDS bytes), queried once per shape and
+// cached, so that a step being captured into a graph makes no runtime query.
 static int occupancy_for(int NP, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<int, size_t>, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find({NP, lds});
+  if (it != cache.end()) return it->second;
   int blocks = 0;
   hipError_t e;
   switch (NP) {
@@ -506,53 +516,72 @@ static int occupancy_for(int NP, size_t lds) {
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_kernel<32>, 64, lds); break;
   }
   if (e != hipSuccess || blocks < 1) blocks = 1;
+  cache[{NP, lds}] = blocks;
   return blocks;
 }
 
 // Per-wave LDS budget of the scan: the genome window plus the tile's codes.
 static constexpr size_t kScanLdsBudget = 40 * 1024;
 
-// Tile shape: the widest wave segment (128*NP offsets) that divides F, read
-// tiles of R reads (bounded by the LDS budget) and enough fragment chunks to
-// give every resident wave several work items.
-static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride) {
-  Tiles t{};
+static int np_for(const Index* ix, const TileOverride* force) {
   const uint32_t F = ix->F;
-  if (F % 4096 == 0) t.NP = 32;
-  else if (F % 2048 == 0) t.NP = 16;
-  else t.NP = 8;
+  if (force && (force->NP == 8 || force->NP == 16 || force->NP == 32)) return force->NP;
+  if (F % 4096 == 0) return 32;
+  if (F % 2048 == 0) return 16;
+  return 8;
+}
+
+// Tile shape: the widest wave segment (128*NP offsets) that divides F, read
+// tiles of R reads (bounded by the LDS budget) and a fragment-chunk count
+// that fills whole rounds of the resident waves.  partial_cap (0 = none)
+// bounds reads x chunks, the size of the per-chunk top-2 buffer.
+static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
+                          const TileOverride* force, uint64_t partial_cap) {
+  if (!force) force = &ix->tune;
+  Tiles t{};
+  t.NP = np_for(ix, force);
   const uint32_t S = 128u * t.NP;
-  t.nseg = (F + S - 1) / S;
+  t.nseg = (ix->F + S - 1) / S;
   t.win_slots = win_slots_for(t.NP, mstride);
   t.cw = mstride / 8 + (uint32_t)t.NP / 8 + 1;
   const size_t win_bytes = (size_t)t.win_slots * 4u;
   const size_t per_read = (size_t)2 * t.cw * 4u;
-  t.R = 32;
-  while (t.R > 1 && win_bytes + t.R * per_read > kScanLdsBudget) t.R /= 2;
+  uint32_t rmax = 32;
+  while (rmax > 1 && win_bytes + rmax * per_read > kScanLdsBudget) rmax /= 2;
+  if (win_bytes + rmax * per_read > 64 * 1024 && rmax > 1) rmax = 1;
+  t.R = force->R ? (force->R < rmax ? force->R : rmax) : rmax;
   t.lds = win_bytes + t.R * per_read;
   const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.lds);
-  while (t.R > 4 && (uint64_t)((n + t.R - 1) / t.R) * ix->NF < 4ull * resident) t.R /= 2;
+  if (!force->R)
+    while (t.R > 4 && (uint64_t)((n + t.R - 1) / t.R) * ix->NF < 4ull * resident) t.R /= 2;
   t.lds = win_bytes + t.R * per_read;
   t.ntiles = (n + t.R - 1) / t.R;
   // Chunk count: items of equal cost run in rounds of `resident` waves, so
-  // pick the count whose item total best fills whole rounds (at least 8
-  // rounds when the work allows it; fewer, larger items on ties).
+  // pick the count whose item total best fills whole rounds (at least
+  // `rounds` rounds when the work allows it; fewer, larger items on ties).
+  const uint32_t rounds = force->rounds ? force->rounds : 8;
   uint32_t best_c = 1;
   double best_eff = -1.0;
-  const uint64_t min_items = 8ull * resident;
-  uint32_t c_lo = (uint32_t)((min_items + t.ntiles - 1) / t.ntiles);
-  if (c_lo < 1) c_lo = 1;
-  if (c_lo > ix->NF) c_lo = ix->NF;
-  const uint32_t c_hi = c_lo * 4 < ix->NF ? c_lo * 4 : ix->NF;
+  const uint64_t min_items = (uint64_t)rounds * resident;
+  uint64_t c_lo64 = (min_items + t.ntiles - 1) / t.ntiles;
+  if (c_lo64 < 1) c_lo64 = 1;
+  if (c_lo64 > ix->NF) c_lo64 = ix->NF;
+  uint32_t c_lo = (uint32_t)c_lo64;
+  uint32_t c_hi = c_lo * 4 < ix->NF ? c_lo * 4 : ix->NF;
+  if (partial_cap) {
+    const uint64_t cmax = partial_cap / (n ? n : 1);
+    if (cmax < 1) c_hi = 1;
+    else if (c_hi > cmax) c_hi = (uint32_t)cmax;
+    if (c_lo > c_hi) c_lo = c_hi;
+  }
   for (uint32_t c = c_lo; c <= c_hi; c++) {
     const uint32_t C = (ix->NF + c - 1) / c;
     const uint32_t nch = (ix->NF + C - 1) / C;
     const double full = (double)t.ntiles * (nch - 1) * C +
                         (double)t.ntiles * (ix->NF - (uint64_t)(nch - 1) * C);
-    const double unit = (double)C;  // cost of one full item, in fragments
     const double per_wave = full / resident;
-    const double rounds = std::ceil(per_wave / unit - 1e-9);
-    const double eff = per_wave / (rounds * unit);
+    const double rnd = std::ceil(per_wave / C - 1e-9);
+    const double eff = per_wave / (rnd * C);
     if (eff > best_eff + 1e-3) {
       best_eff = eff;
       best_c = nch;
@@ -560,10 +589,117 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride) {
   }
   t.C = (ix->NF + best_c - 1) / best_c;
   t.nchunks = (ix->NF + t.C - 1) / t.C;
-  uint64_t total = (uint64_t)t.ntiles * t.nchunks;
+  const uint64_t total = (uint64_t)t.ntiles * t.nchunks;
   t.grid = (uint32_t)(total < resident ? total : resident);
   if (t.grid < 1) t.grid = 1;
   return t;
+}
+
+uint64_t scan_partial_entries(const Index* ix, uint32_t n, const TileOverride* force) {
+  const Tiles t = choose_tiles(ix, n, read_stride(ix), force, 0);
+  return (uint64_t)n * t.nchunks;
+}
+
+maxss_status alloc_scan_work(const Index* ix, uint32_t n, uint64_t partial_cap, bool stream_ordered,
+                             hipStream_t st, ScanWork* w) {
+  maxss_status s;
+  const uint32_t nb = ix->p.max_read_len + 1;
+  w->partial_cap = partial_cap;
+  if (stream_ordered) {
+    if ((s = alloc_encoded(ix, n, st, &w->er))) return s;
+    if ((s = check_hip(hipMallocAsync((void**)&w->order, sizeof(uint32_t) * n, st), "alloc order")) ||
+        (s = check_hip(hipMallocAsync((void**)&w->hist, sizeof(uint32_t) * nb, st), "alloc hist")) ||
+        (s = check_hip(hipMallocAsync((void**)&w->ctr, sizeof(uint32_t), st), "alloc counter")) ||
+        (s = check_hip(hipMallocAsync((void**)&w->partial, sizeof(int4) * partial_cap, st),
+                       "alloc partial")))
+      return s;
+    return MAXSS_OK;
+  }
+  w->er.mstride = read_stride(ix);
+  const uint64_t nw = (uint64_t)n * 2 * (w->er.mstride / 8) + 64;
+  if ((s = check_hip(hipMalloc((void**)&w->er.sel4, sizeof(uint32_t) * nw), "alloc read codes")) ||
+      (s = check_hip(hipMalloc((void**)&w->er.codes, (uint64_t)n * w->er.mstride + 64),
+                     "alloc read bases")) ||
+      (s = check_hip(hipMalloc((void**)&w->er.lens, sizeof(uint32_t) * ((uint64_t)n + 1)),
+                     "alloc lens")) ||
+      (s = check_hip(hipMalloc((void**)&w->order, sizeof(uint32_t) * n), "alloc order")) ||
+      (s = check_hip(hipMalloc((void**)&w->hist, sizeof(uint32_t) * nb), "alloc hist")) ||
+      (s = check_hip(hipMalloc((void**)&w->ctr, sizeof(uint32_t)), "alloc counter")) ||
+      (s = check_hip(hipMalloc((void**)&w->partial, sizeof(int4) * partial_cap), "alloc partial")))
+    return s;
+  return MAXSS_OK;
+}
+
+void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st) {
+  void* ps[] = {w->order, w->hist, w->ctr, w->partial};
+  for (void* p : ps) {
+    if (!p) continue;
+    if (stream_ordered) (void)hipFreeAsync(p, st);
+    else (void)hipFree(p);
+  }
+  if (stream_ordered) {
+    release_encoded(&w->er, st);
+  } else {
+    if (w->er.sel4) (void)hipFree(w->er.sel4);
+    if (w->er.codes) (void)hipFree(w->er.codes);
+    if (w->er.lens) (void)hipFree(w->er.lens);
+    w->er = EncodedReads{};
+  }
+  w->order = w->hist = w->ctr = nullptr;
+  w->partial = nullptr;
+}
+
+maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* dout,
+                           const ScanWork& w, const TileOverride* force, hipStream_t st) {
+  const uint32_t n = r.n;
+  if (n == 0) return MAXSS_OK;
+  maxss_status s;
+  const uint32_t nstrands = (ix->p.flags & MAXSS_ONE_STRAND) ? 1u : 2u;
+  const EncodedReads& er = w.er;
+  if ((s = encode_reads_into(ix, r, st, er))) return s;
+  const uint32_t mstride = er.mstride;
+  Tiles t = choose_tiles(ix, n, mstride, force, w.partial_cap);
+  if ((uint64_t)n * t.nchunks > w.partial_cap)
+    return fail(MAXSS_ESTATE, "partial buffer too small (%llu < %llu)",
+                (unsigned long long)w.partial_cap, (unsigned long long)n * t.nchunks);
+  const uint32_t M8 = (uint32_t)ix->p.match & 0xFFu, X8 = (uint32_t)ix->p.mismatch & 0xFFu;
+  const uint64_t sx = ix->p.mismatch < 0 ? 0xFFull : 0ull;
+  // all-mismatch pool: bytes [X, X, sign(X), X, 0, X, 0, X]
+  const uint64_t xpool = (uint64_t)X8 | ((uint64_t)X8 << 8) | (sx << 16) | ((uint64_t)X8 << 24) |
+                         ((uint64_t)X8 << 40) | ((uint64_t)X8 << 56);
+  // reads ordered by length, longest first
+  const uint32_t nb = ix->p.max_read_len + 1;
+  fill_u32_kernel<<<(nb + 255) / 256, 256, 0, st>>>(w.hist, 0u, nb);
+  len_hist_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, w.hist);
+  len_starts_kernel<<<1, 1024, 0, st>>>(w.hist, nb);
+  len_scatter_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, w.hist, w.order);
+  fill_u32_kernel<<<1, 64, 0, st>>>(w.ctr, 0u, 1u);
+  if ((s = check_hip(hipGetLastError(), "length sort"))) return s;
+  ScanArgs a{};
+  a.g2 = ix->g2; a.nmask = ix->nmask; a.Lpad = ix->Lpad;
+  a.F = ix->F; a.NF = ix->NF; a.nseg = t.nseg;
+  a.sel4 = er.sel4; a.cwg = mstride / 8; a.cw = t.cw; a.win_slots = t.win_slots;
+  a.xpool = xpool; a.dpool = (uint64_t)(M8 ^ X8);
+  a.lens = er.lens; a.order = w.order; a.n = n;
+  a.R = t.R; a.ntiles = t.ntiles; a.C = t.C; a.nchunks = t.nchunks;
+  a.total_work = t.ntiles * t.nchunks; a.work_ctr = w.ctr; a.partial = w.partial;
+  a.nstrands = nstrands; a.mp_max = mstride;
+  if (t.NP == 8) s = launch_scan<8>(a, t.grid, t.lds, st);
+  else if (t.NP == 16) s = launch_scan<16>(a, t.grid, t.lds, st);
+  else s = launch_scan<32>(a, t.grid, t.lds, st);
+  if (s) return s;
+  {
+    ProfScope prof("merge", st);
+    merge_kernel<<<(n + 255) / 256, 256, 0, st>>>(w.partial, t.nchunks, er.lens, n, dout);
+  }
+  if ((s = check_hip(hipGetLastError(), "merge_kernel"))) return s;
+  const size_t rl = (size_t)ix->F + 3 * (size_t)mstride + 16;
+  {
+    ProfScope prof("rescan", st);
+    rescan_kernel<<<dim3(n, 2), 256, rl, st>>>(ix->codes, ix->F, er.codes, er.lens, mstride,
+                                               ix->p.match, ix->p.mismatch, nstrands, n, dout);
+  }
+  return check_hip(hipGetLastError(), "rescan_kernel");
 }
 
 }  // namespace maxss
@@ -585,85 +721,26 @@ extern "C" maxss_status maxss_scan_reads(const maxss_index* index, const maxss_r
   if (cur != ix->device) return fail(MAXSS_ESTATE, "index lives on device %d, current is %d",
                                      ix->device, cur);
   DeviceReads dr;
-  EncodedReads er;
-  uint32_t* order = nullptr;
-  uint32_t* ctr = nullptr;
-  int4* partial = nullptr;
+  ScanWork w;
   maxss_top2* dout = nullptr;
   const uint32_t n = reads->n;
-  const uint32_t nstrands = (ix->p.flags & MAXSS_ONE_STRAND) ? 1u : 2u;
   do {
     if ((s = stage_reads(reads, st, &dr))) break;
-    if ((s = encode_reads(ix, dr, st, &er))) break;
-    const uint32_t mp_max = er.mstride;
-    Tiles t = choose_tiles(ix, n, mp_max);
-    const uint32_t M8 = (uint32_t)ix->p.match & 0xFFu, X8 = (uint32_t)ix->p.mismatch & 0xFFu;
-    const uint64_t sx = ix->p.mismatch < 0 ? 0xFFull : 0ull;
-    // all-mismatch pool: bytes [X, X, sign(X), X, 0, X, 0, X]
-    const uint64_t xpool = (uint64_t)X8 | ((uint64_t)X8 << 8) | (sx << 16) | ((uint64_t)X8 << 24) |
-                           ((uint64_t)X8 << 40) | ((uint64_t)X8 << 56);
-    if ((s = check_hip(hipMallocAsync((void**)&order, sizeof(uint32_t) * n, st), "alloc order")))
-      break;
-    if ((s = check_hip(hipMallocAsync((void**)&ctr, sizeof(uint32_t), st), "alloc counter")))
-      break;
-    if ((s = check_hip(hipMallocAsync((void**)&partial, sizeof(int4) * (uint64_t)n * t.nchunks, st),
-                       "alloc partial")))
-      break;
+    if ((s = alloc_scan_work(ix, n, scan_partial_entries(ix, n, nullptr), true, st, &w))) break;
     if (reads->on_device) {
       dout = out;
     } else if ((s = check_hip(hipMallocAsync((void**)&dout, sizeof(maxss_top2) * n, st),
                               "alloc out"))) {
       break;
     }
-    // reads ordered by length, longest first
-    const uint32_t nb = ix->p.max_read_len + 1;
-    uint32_t* hist = nullptr;
-    if ((s = check_hip(hipMallocAsync((void**)&hist, sizeof(uint32_t) * nb, st), "alloc hist")))
+    if ((s = scan_pipeline(ix, dr, dout, w, nullptr, st))) break;
+    if (!reads->on_device &&
+        (s = check_hip(hipMemcpyAsync(out, dout, sizeof(maxss_top2) * n, hipMemcpyDeviceToHost, st),
+                       "copy results")))
       break;
-    fill_u32_kernel<<<(nb + 255) / 256, 256, 0, st>>>(hist, 0u, nb);
-    len_hist_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, hist);
-    len_starts_kernel<<<1, 1024, 0, st>>>(hist, nb);
-    len_scatter_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, hist, order);
-    (void)hipFreeAsync(hist, st);
-    if ((s = check_hip(hipGetLastError(), "length sort"))) break;
-    fill_u32_kernel<<<1, 64, 0, st>>>(ctr, 0u, 1u);
-    ScanArgs a{};
-    a.g2 = ix->g2; a.nmask = ix->nmask; a.Lpad = ix->Lpad;
-    a.F = ix->F; a.NF = ix->NF; a.nseg = t.nseg;
-    a.sel4 = er.sel4; a.cwg = er.mstride / 8; a.cw = t.cw; a.win_slots = t.win_slots;
-    a.xpool = xpool; a.dpool = (uint64_t)(M8 ^ X8);
-    a.lens = er.lens; a.order = order; a.n = n;
-    a.R = t.R; a.ntiles = t.ntiles; a.C = t.C; a.nchunks = t.nchunks;
-    a.total_work = t.ntiles * t.nchunks; a.work_ctr = ctr; a.partial = partial;
-    a.nstrands = nstrands; a.mp_max = mp_max;
-    const size_t lds = t.lds;
-    if (t.NP == 8) s = launch_scan<8>(a, t.grid, lds, st);
-    else if (t.NP == 16) s = launch_scan<16>(a, t.grid, lds, st);
-    else s = launch_scan<32>(a, t.grid, lds, st);
-    if (s) break;
-    {
-      ProfScope prof("merge", st);
-      merge_kernel<<<(n + 255) / 256, 256, 0, st>>>(partial, t.nchunks, er.lens, n, dout);
-    }
-    if ((s = check_hip(hipGetLastError(), "merge_kernel"))) break;
-    const size_t rl = (size_t)ix->F + er.mstride + 2 * er.mstride + 16;
-    {
-      ProfScope prof("rescan", st);
-      rescan_kernel<<<dim3(n, 2), 256, rl, st>>>(ix->codes, ix->F, er.codes, er.lens, er.mstride,
-                                                 ix->p.match, ix->p.mismatch, nstrands, n, dout);
-    }
-    if ((s = check_hip(hipGetLastError(), "rescan_kernel"))) break;
-    if (!reads->on_device) {
-      if ((s = check_hip(hipMemcpyAsync(out, dout, sizeof(maxss_top2) * n, hipMemcpyDeviceToHost, st),
-                         "copy results")))
-        break;
-    }
   } while (0);
-  if (order) (void)hipFreeAsync(order, st);
-  if (ctr) (void)hipFreeAsync(ctr, st);
-  if (partial) (void)hipFreeAsync(partial, st);
   if (dout && dout != out) (void)hipFreeAsync(dout, st);
-  release_encoded(&er, st);
+  release_scan_work(&w, true, st);
   release_reads(&dr, st);
   if (!reads->on_device && s == MAXSS_OK) s = check_hip(hipStreamSynchronize(st), "sync");
   return s;
