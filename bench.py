@@ -62,6 +62,66 @@ def cpu_baseline(w, budget_s: float = 15.0):
                 k, w.reads.n, dt)}
 
 
+def proposal_leg(ix, w, seq, off, top_full, stream, args):
+    """Learned proposal on the bacterial genome: train on plain-scan labels of
+    `train_reads` reads (own seed), choose the margin threshold on a 10%
+    held-out split for >= 99.5% top-1 agreement there, then time the
+    proposal path and the full scan on the workload's reads (already in HBM)
+    and report reads/s and top-1 agreement with the full scan."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1403_2136_amd as mx
+    from paper_1403_2136_amd import proposal as P
+    t0 = time.time()
+    tw = gen.workload("proposal_train", n_reads=args.train_reads)
+    nval = tw.reads.n // 10
+    val = tw.reads.subset(np.arange(nval))
+    trn = tw.reads.subset(np.arange(nval, tw.reads.n))
+    dtr, dva = P.DeviceReads(trn.seq, trn.offsets), P.DeviceReads(val.seq, val.offsets)
+    ltr, lva = P.scan_labels(ix, dtr), P.scan_labels(ix, dva)
+    t_label = time.time() - t0
+    model = mx.Model(gen.mlp_init(43))
+    t1 = time.time()
+    losses = P.train(ix, model, dtr, ltr, steps=args.train_steps, batch=256, lr=2e-3, seed=44,
+                     log=None)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    c, mg, fb = P.candidates(ix, model, dva, args.K)
+    tau = P.choose_margin(c, mg, lva, 0.995)
+    log("proposal: labels %.1fs, %d steps in %.1fs (loss %.3f -> %.3f), val recall@%d %.4f, "
+        "tau %.4f" % (t_label, args.train_steps, t_train, losses[0][1], losses[-1][1], args.K,
+                      P.recall(c, lva).mean(), tau))
+    n = w.reads.n
+    out = torch.empty(n * 32, dtype=torch.uint8, device="cuda")
+    fbt = torch.empty(n, dtype=torch.uint8, device="cuda")
+    model.scan(ix, seq, off, args.K, tau, out, fbt, stream=stream)   # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t2 = time.perf_counter()
+    for _ in range(reps):
+        model.scan(ix, seq, off, args.K, tau, out, fbt, stream=stream)
+    torch.cuda.synchronize()
+    t_prop = (time.perf_counter() - t2) / reps
+    t3 = time.perf_counter()
+    ix.scan(seq, off, top_full, stream=stream)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t3
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    ref = top_full.cpu().numpy().view(mx.TOP2_DTYPE)
+    res = {"reads_per_s": round(n / t_prop, 1), "full_scan_reads_per_s": round(n / t_full, 1),
+           "speedup": round(t_full / t_prop, 3), "top1_agreement": round(P.top1_agreement(got, ref), 5),
+           "score_agreement": round(P.score_agreement(got, ref), 5),
+           "fallback_rate": round(float(fbt.cpu().numpy().mean()), 4), "K": args.K,
+           "tau": round(tau, 5), "train_reads": trn.n, "train_steps": args.train_steps,
+           "train_s": round(t_train, 2), "label_s": round(t_label, 2),
+           "val_recall_at_K": round(float(P.recall(c, lva).mean()), 5)}
+    log("proposal: %s" % res)
+    model.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +132,11 @@ def main():
     ap.add_argument("--reads", type=int, default=None, help="override the read count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-proposal", action="store_true",
+                    help="skip the learned-proposal leg (training + reads/s vs the full scan)")
+    ap.add_argument("--train-reads", type=int, default=200_000)
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "known-size kernel that scales the HBM byte counters)")
@@ -115,25 +180,52 @@ def main():
     G = w.genome.G
     cells = 2.0 * G * float(w.reads.lengths().sum())
 
-    def step():
-        ix.scan(seq, off, top, stream=stream)
-        ix.align(seq, off, top, w.pad, stride, aln, cig, stream=stream)
+    batched = w.name in ("chromosome", "damaged")
+    tune = None
+    if batched:
+        # one persistent scan launch per mixed-length batch, replayed from a
+        # captured HIP graph; tiles from the autotuner (parity-gated)
+        sample = w.reads.subset(np.arange(0, n, max(1, n // 2000))[:2000])
+        tune = ix.autotune(sample.seq, sample.offsets)
+        log("autotune: %s" % tune)
+        plan = mx.Plan(ix, capacity=n, pad=w.pad, cigar_stride=stride)
+        stream = torch.cuda.Stream()
 
+        def step(graph=True):
+            with torch.cuda.stream(stream):
+                plan.run(seq, off, top, aln, cig, stream=stream, graph=graph)
+    else:
+        def step(graph=False):
+            ix.scan(seq, off, top, stream=stream)
+            ix.align(seq, off, top, w.pad, stride, aln, cig, stream=stream)
+
+    if batched:
+        # one eager step with kernel events (graph replays carry none)
+        mx.maxss_profile_enable(True)
+        step(graph=False)
+        torch.cuda.synchronize()
+        scan_ms, scan_k = mx.maxss_profile_read("scan")
+        nw_ms, nw_k = mx.maxss_profile_read("nw")
+        other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
+        mx.maxss_profile_enable(False)
+        log("eager step: scan %.1f ms" % scan_ms)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log("warmup %d done" % i)
-    mx.maxss_profile_enable(True)
+    if not batched:
+        mx.maxss_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    scan_ms, scan_k = mx.maxss_profile_read("scan")
-    nw_ms, nw_k = mx.maxss_profile_read("nw")
-    other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
-    mx.maxss_profile_enable(False)
+    if not batched:
+        scan_ms, scan_k = mx.maxss_profile_read("scan")
+        nw_ms, nw_k = mx.maxss_profile_read("nw")
+        other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
+        mx.maxss_profile_enable(False)
     log("timed %d steps in %.3fs; scan kernel %.3f ms/launch, nw %.3f ms/launch, %s" % (
         args.steps, dt, scan_ms / max(scan_k, 1), nw_ms / max(nw_k, 1),
         {k: round(v[0] / max(v[1], 1), 3) for k, v in other.items()}))
@@ -164,6 +256,8 @@ def main():
             "scan_gcups_kernel": round(cells / scan_s / 1e9, 1),
             "scan_ms_per_launch": round(scan_s * 1e3, 3),
             "nw_ms_per_launch": round(nw_ms / max(nw_k, 1), 3),
+            "step_path": "plan + hipGraph replay, autotuned tiles" if batched else
+                         "maxss_scan_reads + maxss_align_top",
         },
         "roofline": {
             "bound": "alu",
@@ -174,6 +268,10 @@ def main():
             "traffic": None,
         },
     }
+    if tune is not None:
+        res["config"]["autotune"] = tune
+    if not args.no_proposal and w.name == "bacterial":
+        res["proposal"] = proposal_leg(ix, w, seq, off, top, stream, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

@@ -380,3 +380,56 @@ def workload(name: str, n_reads: int | None = None, read_seed: int | None = None
                          indel_max=1, damage=True, length_mode="range")
         return Workload(name, g, r, F=4096, max_read_len=80)
     raise KeyError(name)
+
+
+# ------------------------------------------------- learned-proposal inputs
+
+def mlp_init(seed: int, d: int = 256, hidden: int = 256) -> np.ndarray:
+    """Initial parameters of the 512-256-1 proposal network (float32, layout
+    W1 row-major, b1, w2, b2): W1 and w2 uniform in +-sqrt(6/(fan_in+fan_out))
+    (Glorot & Bengio, 2010), biases 0."""
+    st = Stream(seed, "mlp.init")
+    a1 = np.sqrt(6.0 / (2 * d + hidden))
+    a2 = np.sqrt(6.0 / (hidden + 1))
+    W1 = (st.uniform(hidden * 2 * d) * 2 - 1) * a1
+    w2 = (st.uniform(hidden) * 2 - 1) * a2
+    return np.concatenate([W1, np.zeros(hidden), w2, [0.0]]).astype(np.float32)
+
+
+def sample_negatives(seed: int, step: int, labels: np.ndarray, second: np.ndarray, NF: int,
+                     n_neg: int = 63) -> np.ndarray:
+    """Negative fragments for a batch (B, n_neg) int32: the second-best
+    fragment first when it exists and differs from the label, then distinct
+    uniform draws over the fragments other than the label (repeats only when
+    fewer than n_neg other fragments exist)."""
+    labels = np.asarray(labels, dtype=np.int64)
+    second = np.asarray(second, dtype=np.int64)
+    B = labels.size
+    st = Stream(seed, "train.neg.%d" % step)
+    D = n_neg + 48
+    others = max(NF - 1, 1)
+    x = st.integers(0, others, B * D).reshape(B, D)
+    x = x + (x >= labels[:, None])                        # skip the label
+    x = np.sort(x, axis=1)
+    dup = np.zeros_like(x, dtype=bool)
+    dup[:, 1:] = x[:, 1:] == x[:, :-1]
+    x = np.where(dup, np.iinfo(np.int64).max, x)
+    x = np.sort(x, axis=1)                                # distinct values first
+    has2 = (second >= 0) & (second < NF) & (second != labels)
+    out = np.empty((B, n_neg), dtype=np.int64)
+    out[:, 0] = np.where(has2, second, x[:, 0])
+    rest = x[:, :n_neg]
+    # drop `second` from the uniform draws where it is used, keep order
+    keep = ~((rest == second[:, None]) & has2[:, None])
+    for b in np.nonzero(~keep.all(axis=1))[0]:            # rare: a draw equals `second`
+        row = rest[b][keep[b]]
+        rest[b, :row.size] = row
+        rest[b, row.size:] = x[b, n_neg]
+    start = np.where(has2, 1, 1)
+    out[:, 1:] = np.where(has2[:, None], rest[:, :n_neg - 1], rest[:, 1:n_neg])
+    bad = out >= NF                                        # tiny genomes: too few fragments
+    if bad.any():
+        for b in np.nonzero(bad.any(axis=1))[0]:
+            pool = [f for f in range(NF) if f != labels[b]] or [int(labels[b])]
+            out[b] = [pool[k % len(pool)] for k in range(n_neg)]
+    return out.astype(np.int32)

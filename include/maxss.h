@@ -231,11 +231,90 @@ maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sample, const
 maxss_status maxss_index_set_tiles(maxss_index* index, int32_t np, uint32_t reads_per_tile,
                                    uint32_t rounds);
 
+/* ---- Learned fragment proposal ----------------------------------------------
+ * Not in the paper.  A small network ranks the fragments of each read from
+ * 4-mer count profiles so that only the best K are scanned exactly; a margin
+ * test sends unclear reads to the full scan.  The scores of scanned
+ * fragments are the exact MaxSS scores of the first phase.
+ *
+ * Profiles: c[j] = number of 4-mers without N with j = 64x0+16x1+4x2+x3
+ * (A0 C1 G2 T3), v = c/||c||_2 (0 if no 4-mer), computed in float64 and
+ * rounded to float32, then to bf16 (nearest even).  Reads: one profile per
+ * strand.  Fragment f: the 4-mers that start in [fF, fF+F).
+ * Network: z = [v_read ; v_frag], h = ReLU(W1 z + b1) (W1: 256 x 512),
+ * y = w2 . h + b2; W1 and w2 in bf16, b1 and b2 in fp32, fp32 accumulation.
+ * Parameters (MAXSS_MLP_PARAMS floats, this order): W1 row-major, b1, w2, b2.
+ * A fragment's score for a read is the max of y over the read's strands. */
+#define MAXSS_MLP_PARAMS 131585
+
+typedef struct maxss_model maxss_model; /* opaque, library-owned */
+
+/* Create a model on the current device from MAXSS_MLP_PARAMS host floats
+ * (fp32 master copy; Adam state zero).  Errors: EINVAL, ENOMEM, EDEVICE. */
+maxss_status maxss_model_create(const float* params, maxss_model** out);
+void maxss_model_free(maxss_model* model);
+
+/* Copy the fp32 master parameters to `out` (host, MAXSS_MLP_PARAMS floats). */
+maxss_status maxss_model_get_params(const maxss_model* model, float* out);
+
+/* Save / load parameters, Adam state and step count (binary, format
+ * version 1).  Errors: EINVAL (I/O, bad file), ENOMEM, EDEVICE. */
+maxss_status maxss_model_save(const maxss_model* model, const char* path);
+maxss_status maxss_model_load(const char* path, maxss_model** out);
+
+/* The fp32 profiles (before bf16 rounding): read_prof (device, n*2*256,
+ * strand-major per read) of device reads, and/or frag_prof (device,
+ * NF*256).  Either may be NULL (reads may be NULL with read_prof NULL).
+ * Asynchronous on `stream`.  Errors: EINVAL, ENOMEM, EDEVICE. */
+maxss_status maxss_profiles(const maxss_index* index, const maxss_reads* reads, float* read_prof,
+                            float* frag_prof, void* stream);
+
+/* Network score of every (read, fragment): scores (device, n*NF floats,
+ * read-major) = max over strands of y.  Device reads.  Errors: as above. */
+maxss_status maxss_proposal_scores(const maxss_index* index, maxss_model* model,
+                                   const maxss_reads* reads, float* scores, void* stream);
+
+/* First phase through the proposal: per read, the K fragments with the
+ * highest scores (ties to the smaller id) are scanned exactly and the top-2
+ * among them are reported; a read whose two best scores differ by less than
+ * `margin` is scanned in full instead (fell_back[i] = 1; device, may be
+ * NULL).  Records have the layout and tie rules of maxss_scan_reads; they
+ * equal the full scan's whenever its top-2 fragments are among the K.
+ * Device reads.  Errors: EINVAL (K = 0 or > 4096), ENOMEM, EDEVICE. */
+maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxss_model* model,
+                                       const maxss_reads* reads, uint32_t K, float margin,
+                                       maxss_top2* out, uint8_t* fell_back, void* stream);
+
+/* The proposal alone: per read, the K candidate fragments (device, n*K
+ * int32, ascending ids; -1 past min(K, NF)), the margin between the two best
+ * scores (device, n floats; +inf with one fragment) and the fall-back flag
+ * (margin < `margin`, invalid reads never fall back).  Device reads.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+maxss_status maxss_proposal_candidates(const maxss_index* index, maxss_model* model,
+                                       const maxss_reads* reads, uint32_t K, float margin,
+                                       int32_t* cand, float* margins, uint8_t* fell_back,
+                                       void* stream);
+
+/* One training step on a batch of B device reads: cand (device, B*64 int32)
+ * holds, per read, the label fragment first and 63 other fragments; strand
+ * (device, B int8) the label strand, whose profile is used for all 64
+ * pairs.  Loss: mean over reads of the softmax cross-entropy of the 64
+ * scores with the label at position 0.  Writes the mean loss to `loss`
+ * (device float, may be NULL) and the gradient to `grad` (device,
+ * MAXSS_MLP_PARAMS floats, may be NULL); then, if lr > 0, one Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on the fp32 master weights and a
+ * refresh of the bf16 copies.  Errors: EINVAL, ENOMEM, EDEVICE. */
+maxss_status maxss_model_train_step(maxss_model* model, const maxss_index* index,
+                                    const maxss_reads* batch, const int32_t* cand,
+                                    const int8_t* strand, float lr, float* loss, float* grad,
+                                    void* stream);
+
 /* Kernel timing for measurement.  maxss_profile_enable(1) clears the records
  * and brackets every later launch of the library's kernels with HIP events on
  * the launch stream; maxss_profile_enable(0) stops recording.
  * maxss_profile_read waits for the recorded events of the kernel `name`
- * ("encode", "scan", "merge", "rescan", "nw") and returns their summed
+ * ("encode", "scan", "merge", "rescan", "nw", "profile", "gemm", "pair",
+ * "topk") and returns their summed
  * duration in milliseconds and the number of launches.  Not for use while a
  * stream is being captured into a graph.  Errors: EINVAL (NULL), EDEVICE. */
 maxss_status maxss_profile_enable(int on);

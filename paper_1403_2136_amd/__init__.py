@@ -65,7 +65,11 @@ class Reads(ctypes.Structure):
 EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_scan_reads",
            "maxss_align_top", "maxss_plan_create", "maxss_plan_free", "maxss_plan_run",
            "maxss_plan_run_graph", "maxss_autotune", "maxss_index_set_tiles",
+           "maxss_model_create", "maxss_model_free", "maxss_model_get_params", "maxss_model_save",
+           "maxss_model_load", "maxss_profiles", "maxss_proposal_scores",
+           "maxss_proposal_candidates", "maxss_scan_reads_proposed", "maxss_model_train_step",
            "maxss_profile_enable", "maxss_profile_read", "maxss_last_error", "maxss_version")
+MLP_PARAMS = 131585
 
 _lib = None
 
@@ -110,6 +114,34 @@ def lib():
                                      c.POINTER(TuneResult)]
         L.maxss_index_set_tiles.restype = c.c_int
         L.maxss_index_set_tiles.argtypes = [c.c_void_p, c.c_int32, c.c_uint32, c.c_uint32]
+        L.maxss_model_create.restype = c.c_int
+        L.maxss_model_create.argtypes = [c.c_void_p, c.POINTER(c.c_void_p)]
+        L.maxss_model_free.restype = None
+        L.maxss_model_free.argtypes = [c.c_void_p]
+        L.maxss_model_get_params.restype = c.c_int
+        L.maxss_model_get_params.argtypes = [c.c_void_p, c.c_void_p]
+        L.maxss_model_save.restype = c.c_int
+        L.maxss_model_save.argtypes = [c.c_void_p, c.c_char_p]
+        L.maxss_model_load.restype = c.c_int
+        L.maxss_model_load.argtypes = [c.c_char_p, c.POINTER(c.c_void_p)]
+        L.maxss_profiles.restype = c.c_int
+        L.maxss_profiles.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p, c.c_void_p,
+                                     c.c_void_p]
+        L.maxss_proposal_scores.restype = c.c_int
+        L.maxss_proposal_scores.argtypes = [c.c_void_p, c.c_void_p, c.POINTER(Reads), c.c_void_p,
+                                            c.c_void_p]
+        L.maxss_proposal_candidates.restype = c.c_int
+        L.maxss_proposal_candidates.argtypes = [c.c_void_p, c.c_void_p, c.POINTER(Reads),
+                                                c.c_uint32, c.c_float, c.c_void_p, c.c_void_p,
+                                                c.c_void_p, c.c_void_p]
+        L.maxss_scan_reads_proposed.restype = c.c_int
+        L.maxss_scan_reads_proposed.argtypes = [c.c_void_p, c.c_void_p, c.POINTER(Reads),
+                                                c.c_uint32, c.c_float, c.c_void_p, c.c_void_p,
+                                                c.c_void_p]
+        L.maxss_model_train_step.restype = c.c_int
+        L.maxss_model_train_step.argtypes = [c.c_void_p, c.c_void_p, c.POINTER(Reads), c.c_void_p,
+                                             c.c_void_p, c.c_float, c.c_void_p, c.c_void_p,
+                                             c.c_void_p]
         L.maxss_profile_enable.restype = c.c_int
         L.maxss_profile_enable.argtypes = [c.c_int]
         L.maxss_profile_read.restype = c.c_int
@@ -190,6 +222,18 @@ def maxss_index_info(handle: int):
     return G.value, NF.value, F.value
 
 
+def _host_csr(seq, offsets):
+    """Host reads as (uint8 array, uint64 offsets), with the offsets checked
+    against the buffer so that the library never reads past it."""
+    s = _as_u8(seq)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if off.ndim != 1 or off.size < 1:
+        raise ValueError("offsets must have n+1 >= 1 entries")
+    if off.size > 1 and (int(off[-1]) > s.size or (np.diff(off.astype(np.int64)) < 0).any()):
+        raise ValueError("offsets must be non-decreasing and end within the sequence buffer")
+    return s, off
+
+
 def _reads_struct(seq, offsets, on_device: bool) -> Reads:
     n = (offsets.numel() if hasattr(offsets, "numel") else len(offsets)) - 1
     return Reads(_ptr(seq), _ptr(offsets), n, 1 if on_device else 0)
@@ -209,8 +253,7 @@ def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None):
         _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), _ptr(out),
                                       _stream_handle(stream)))
         return out
-    s = _as_u8(seq)
-    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    s, off = _host_csr(seq, offsets)
     n = off.size - 1
     res = np.zeros(n, dtype=TOP2_DTYPE) if out is None else out
     r = Reads(s.ctypes.data, off.ctypes.data, n, 0)
@@ -228,8 +271,7 @@ def maxss_align_top(handle: int, seq, offsets, top, pad: int = 100, cigar_stride
         _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), _ptr(top), pad, _ptr(out),
                                      _ptr(cigar), cigar_stride, _stream_handle(stream)))
         return out, cigar
-    s = _as_u8(seq)
-    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    s, off = _host_csr(seq, offsets)
     n = off.size - 1
     top = np.ascontiguousarray(top, dtype=TOP2_DTYPE)
     res = np.zeros(n, dtype=ALN_DTYPE)
@@ -268,8 +310,7 @@ def maxss_autotune(handle, seq, offsets, cache_path: str | None = None) -> dict:
         r = _reads_struct(seq, offsets, True)
         keep = None
     else:
-        s = _as_u8(seq)
-        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        s, off = _host_csr(seq, offsets)
         r = Reads(s.ctypes.data, off.ctypes.data, off.size - 1, 0)
         keep = (s, off)
     _check(lib().maxss_autotune(h_(handle), ctypes.byref(r),
@@ -316,6 +357,71 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Model:
+    """Owner of a proposal network (fp32 master + bf16 copies + Adam state)."""
+
+    def __init__(self, params=None, path: str | None = None):
+        h = ctypes.c_void_p()
+        if path is not None:
+            _check(lib().maxss_model_load(path.encode(), ctypes.byref(h)))
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            if p.size != MLP_PARAMS:
+                raise ValueError("expected %d parameters" % MLP_PARAMS)
+            self._init = p
+            _check(lib().maxss_model_create(p.ctypes.data, ctypes.byref(h)))
+        self.handle = h.value
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib().maxss_model_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def save(self, path: str):
+        _check(lib().maxss_model_save(self.handle, path.encode()))
+
+    def scores(self, index, seq, offsets, out, stream=None):
+        r = _reads_struct(seq, offsets, True)
+        _check(lib().maxss_proposal_scores(h_(index), self.handle, ctypes.byref(r), _ptr(out),
+                                           _stream_handle(stream)))
+
+    def candidates(self, index, seq, offsets, K, margin, cand, margins, fell_back, stream=None):
+        r = _reads_struct(seq, offsets, True)
+        _check(lib().maxss_proposal_candidates(h_(index), self.handle, ctypes.byref(r), K,
+                                               margin, _ptr(cand), _ptr(margins), _ptr(fell_back),
+                                               _stream_handle(stream)))
+
+    def scan(self, index, seq, offsets, K, margin, out, fell_back=None, stream=None):
+        r = _reads_struct(seq, offsets, True)
+        _check(lib().maxss_scan_reads_proposed(h_(index), self.handle, ctypes.byref(r), K, margin,
+                                               _ptr(out), _ptr(fell_back),
+                                               _stream_handle(stream)))
+
+    def train_step(self, index, seq, offsets, cand, strand, lr, loss=None, grad=None,
+                   stream=None):
+        r = _reads_struct(seq, offsets, True)
+        _check(lib().maxss_model_train_step(self.handle, h_(index), ctypes.byref(r), _ptr(cand),
+                                            _ptr(strand), lr, _ptr(loss), _ptr(grad),
+                                            _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().maxss_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def maxss_profiles(index, seq=None, offsets=None, read_prof=None, frag_prof=None, stream=None):
+    r = _reads_struct(seq, offsets, True) if seq is not None else None
+    _check(lib().maxss_profiles(h_(index), ctypes.byref(r) if r is not None else None,
+                                _ptr(read_prof), _ptr(frag_prof), _stream_handle(stream)))
 
 
 class Index:

@@ -113,6 +113,16 @@ void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st);
 maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* dout,
                            const ScanWork& w, const TileOverride* force, hipStream_t st);
 
+// First phase on encoded reads with per-read lengths `lens` (0 = skip):
+// the full scan, or (candidate_scan) only each read's Kc first candidates of
+// `cand` (K per read, ascending fragment ids).  Records of skipped reads are
+// invalid.  No allocation.
+maxss_status scan_pipeline_lens(const Index* ix, const EncodedReads& er, const uint32_t* lens,
+                                uint32_t n, maxss_top2* dout, const ScanWork& w, hipStream_t st);
+maxss_status candidate_scan(const Index* ix, const EncodedReads& er, const uint32_t* lens,
+                            uint32_t n, const int32_t* cand, uint32_t K, uint32_t Kc,
+                            maxss_top2* dout, const ScanWork& w, hipStream_t st);
+
 // Second phase scratch and launch (reads already encoded in `er`).
 struct NwShape {
   uint32_t cw = 0, ncols_max = 0, rowbytes = 0, grid = 0;

@@ -1,0 +1,1010 @@
+// Learned fragment proposal: 4-mer profiles, a 512-256-1 MLP in bf16 with
+// fp32 accumulation (MFMA GEMMs + a VALU pair stage), per-read top-K with a
+// margin test, and the MLP's training step (forward, backward, Adam).  HIP,
+// gfx950.  Not in the paper: the proposal only ranks fragments; every
+// fragment that is scanned is scored by the exact MaxSS scan.
+//
+// Network: z = [v_read ; v_frag] (two L2-normalised 256-bin 4-mer count
+// profiles), h = ReLU(W1 z + b1), y = w2 . h + b2.  Inference uses
+// W1 z = W1a v_read + W1b v_frag: A = V_read W1a^T (+ b1) and B = V_frag W1b^T
+// are two bf16 MFMA GEMMs; the pair stage computes sum_k w2[k] ReLU(A + B)
+// for every (read strand, fragment) on the fp32 VALU.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace maxss {
+
+static constexpr int kD = 256;                       // profile bins (4^4)
+static constexpr int kH = 256;                       // hidden units
+static constexpr uint32_t kW1 = kH * 2 * kD;         // 131,072
+static constexpr uint32_t kParams = kW1 + kH + kH + 1;  // 131,585
+static constexpr int kCand = 64;                     // candidates per training read
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __host__ inline uint16_t f2bf(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __host__ inline float bf2f(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
+// ------------------------------------------------------------- profiles
+
+// One wave per profile: counts of the 4-mers without N of a code sequence,
+// normalised in float64 (exact integer sum of squares, correctly rounded
+// sqrt and divide), rounded to float32 and then to bf16.
+// Reads: row = 2*i + s (s = 1: reverse complement of read i).
+// Fragments: row = f, 4-mers starting in [fF, fF+F) of the genome codes.
+__global__ __launch_bounds__(256) void profile_kernel(
+    const uint8_t* __restrict__ rcodes, const uint32_t* __restrict__ lens, uint32_t mstride,
+    uint32_t nreads, const uint8_t* __restrict__ gcodes, uint32_t F, uint32_t NF,
+    uint16_t* __restrict__ out_bf, float* __restrict__ out_f32) {
+  __shared__ int cnt[4][kD];
+  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t row = blockIdx.x * 4 + wv;
+  const uint32_t nrows = rcodes ? 2 * nreads : NF;
+  int* c = cnt[wv];
+  for (int b = lane; b < kD; b += 64) c[b] = 0;
+  __syncthreads();
+  if (row < nrows) {
+    if (rcodes) {
+      const uint32_t i = row >> 1, s = row & 1;
+      const uint32_t m = lens[i];
+      const uint8_t* q = rcodes + (uint64_t)i * mstride;
+      for (uint32_t t = lane; t + 3 < m; t += 64) {
+        uint32_t x0, x1, x2, x3;
+        if (!s) {
+          x0 = q[t]; x1 = q[t + 1]; x2 = q[t + 2]; x3 = q[t + 3];
+        } else {  // reverse complement position t = complement of m-1-t
+          x0 = q[m - 1 - t]; x1 = q[m - 2 - t]; x2 = q[m - 3 - t]; x3 = q[m - 4 - t];
+          x0 = x0 == kN ? kN : 3 - x0; x1 = x1 == kN ? kN : 3 - x1;
+          x2 = x2 == kN ? kN : 3 - x2; x3 = x3 == kN ? kN : 3 - x3;
+        }
+        if (x0 < 4 && x1 < 4 && x2 < 4 && x3 < 4) atomicAdd(&c[64 * x0 + 16 * x1 + 4 * x2 + x3], 1);
+      }
+    } else {
+      const uint64_t base = (uint64_t)row * F;
+      for (uint32_t t = lane; t < F; t += 64) {
+        const uint8_t* g = gcodes + base + t;  // codes past the genome end are N
+        const uint32_t x0 = g[0], x1 = g[1], x2 = g[2], x3 = g[3];
+        if (x0 < 4 && x1 < 4 && x2 < 4 && x3 < 4) atomicAdd(&c[64 * x0 + 16 * x1 + 4 * x2 + x3], 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (row >= nrows) return;
+  long long ss = 0;
+  for (int b = lane; b < kD; b += 64) ss += (long long)c[b] * c[b];
+  for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+  const double nrm = sqrt((double)ss);
+  for (int b = lane; b < kD; b += 64) {
+    const float v = ss > 0 ? (float)((double)c[b] / nrm) : 0.0f;
+    out_bf[(uint64_t)row * kD + b] = f2bf(v);
+    if (out_f32) out_f32[(uint64_t)row * kD + b] = v;
+  }
+}
+
+// ---------------------------------------------------------- MFMA GEMM
+
+// Operand view: element (r, k) = p[(ri ? ri[r] : r) * sr + (ki ? ki[k] : k) * sk]
+// (bf16), with optional row / reduction-index gathers.
+struct Opnd {
+  const uint16_t* p;
+  long long sr, sk;
+  const int32_t* ri;
+  const int32_t* ki;
+};
+
+__device__ inline uint16_t opnd_at(const Opnd& o, int r, int k) {
+  const long long rr = o.ri ? o.ri[r] : r;
+  const long long kk = o.ki ? o.ki[k] : k;
+  return o.p[rr * o.sr + kk * o.sk];
+}
+
+// C[i][j] (+)= sum_k A(i,k) B(j,k) (+ bias[j]), fp32 out (ldc), bf16 in.
+// 256 threads, 64x64 output tile, each wave a 32x32 quarter of 2x2
+// v_mfma_f32_16x16x16_bf16 tiles; K staged through LDS 32 at a time.
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, Opnd A, Opnd B,
+                                                        float* __restrict__ C, long long ldc,
+                                                        const float* __restrict__ bias,
+                                                        int accumulate) {
+  __shared__ uint16_t As[64][36];
+  __shared__ uint16_t Bs[64][36];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  f32x4 acc[2][2];
+  for (int a = 0; a < 2; a++)
+    for (int b = 0; b < 2; b++) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int r = e >> 5, kk = e & 31;
+      const int gi = i0 + r, gj = j0 + r, gk = k0 + kk;
+      As[r][kk] = (gi < M && gk < K) ? opnd_at(A, gi, gk) : (uint16_t)0;
+      Bs[r][kk] = (gj < N && gk < K) ? opnd_at(B, gj, gk) : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 16) {
+      const int ak = kk + (lane >> 4) * 4;
+#pragma unroll
+      for (int ti = 0; ti < 2; ti++) {
+        const int ar = wi + ti * 16 + (lane & 15);
+        const s16x4 a = {(short)As[ar][ak], (short)As[ar][ak + 1], (short)As[ar][ak + 2],
+                         (short)As[ar][ak + 3]};
+#pragma unroll
+        for (int tj = 0; tj < 2; tj++) {
+          const int bc = wj + tj * 16 + (lane & 15);
+          const s16x4 b = {(short)Bs[bc][ak], (short)Bs[bc][ak + 1], (short)Bs[bc][ak + 2],
+                           (short)Bs[bc][ak + 3]};
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ti][tj], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+    for (int tj = 0; tj < 2; tj++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int gi = i0 + wi + ti * 16 + (lane >> 4) * 4 + r;
+        const int gj = j0 + wj + tj * 16 + (lane & 15);
+        if (gi < M && gj < N) {
+          float v = acc[ti][tj][r];
+          if (bias) v += bias[gj];
+          float* cp = C + (long long)gi * ldc + gj;
+          *cp = accumulate ? *cp + v : v;
+        }
+      }
+}
+
+static maxss_status gemm(int M, int N, int K, const Opnd& A, const Opnd& B, float* C, long long ldc,
+                         const float* bias, bool accumulate, hipStream_t st) {
+  if (M <= 0 || N <= 0) return MAXSS_OK;
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  ProfScope prof("gemm", st);
+  gemm_bf16_kernel<<<grid, 256, 0, st>>>(M, N, K, A, B, C, ldc, bias, accumulate ? 1 : 0);
+  return check_hip(hipGetLastError(), "gemm_bf16_kernel");
+}
+
+// ------------------------------------------------------------ pair stage
+
+// S[r][f] = max over strands s of  sum_k w2[k] ReLU(A[2r+s][k] + B[f][k]) + b2
+// for reads [0, n) and fragments [0, NF).  A holds b1 already.  Tile: 32
+// reads (64 A rows) x 64 fragments per 256-thread block; each thread owns
+// 2 reads x 2 strands x 4 fragments.  K staged through LDS, transposed so
+// that every thread reads 4 consecutive words.
+__global__ __launch_bounds__(256) void pair_kernel(const float* __restrict__ A,
+                                                   const float* __restrict__ B,
+                                                   const float* __restrict__ w2, float b2, uint32_t n,
+                                                   uint32_t NF, float* __restrict__ S,
+                                                   uint32_t ldS) {
+  __shared__ float At[32][64];
+  __shared__ float Bt[32][64];
+  __shared__ float ws[32];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t rg = tid >> 4, fg = tid & 15;
+  const uint32_t arow0 = blockIdx.y * 64;   // first A row (= 2 * first read)
+  const uint32_t f0 = blockIdx.x * 64;
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[i][j] = 0.f;
+  for (int k0 = 0; k0 < kH; k0 += 32) {
+    for (uint32_t e = tid; e < 64 * 32; e += 256) {
+      const uint32_t r = e >> 5, kk = e & 31;
+      const uint32_t ar = arow0 + r, fr = f0 + r;
+      At[kk][r] = ar < 2 * n ? A[(uint64_t)ar * kH + k0 + kk] : 0.f;
+      Bt[kk][r] = fr < NF ? B[(uint64_t)fr * kH + k0 + kk] : 0.f;
+    }
+    if (tid < 32) ws[tid] = w2[k0 + tid];
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 32; kk++) {
+      const float w = ws[kk];
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) a[i] = At[kk][rg * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) b[j] = Bt[kk][fg * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = fmaf(w, fmaxf(a[i] + b[j], 0.f), acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const uint32_t r = (arow0 >> 1) + rg * 2 + q;
+    if (r >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const uint32_t f = f0 + fg * 4 + j;
+      if (f < NF) S[(uint64_t)r * ldS + f] = fmaxf(acc[2 * q][j], acc[2 * q + 1][j]) + b2;
+    }
+  }
+}
+
+// ------------------------------------------------------------- top-K
+
+__device__ inline uint64_t score_key(float s, uint32_t f) {
+  uint32_t u = __float_as_uint(s);
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving
+  return ((uint64_t)u << 32) | (0xFFFFFFFFu - f);
+}
+
+// Per read (one 256-thread block): the K largest (score desc, fragment asc)
+// keys by an 8-pass, 8-bit radix select, written as fragment ids in
+// ascending order; margin = best score - second best; fell_back = margin < tau.
+// Reads with lens == 0 (invalid) get no candidates and do not fall back.
+__global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ S, uint32_t ldS,
+                                                   uint32_t NF, uint32_t K, float tau,
+                                                   const uint32_t* __restrict__ lens,
+                                                   uint32_t r0, int32_t* __restrict__ cand,
+                                                   float* __restrict__ margin,
+                                                   uint8_t* __restrict__ fb) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ uint32_t s_need;
+  __shared__ uint64_t red[4][2];
+  __shared__ uint32_t s_base;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t rl = blockIdx.x, r = r0 + rl;
+  const float* row = S + (uint64_t)rl * ldS;
+  const uint32_t Ke = K < NF ? K : NF;
+  // best and second-best keys
+  uint64_t b1 = 0, b2 = 0;
+  for (uint32_t f = tid; f < NF; f += 256) {
+    const uint64_t k = score_key(row[f], f);
+    if (k > b1) { b2 = b1; b1 = k; } else if (k > b2) { b2 = k; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t o1 = __shfl_xor(b1, o, 64), o2 = __shfl_xor(b2, o, 64);
+    const uint64_t n1 = b1 > o1 ? b1 : o1;
+    const uint64_t lo = b1 > o1 ? o1 : b1;
+    const uint64_t m2 = b2 > o2 ? b2 : o2;
+    b2 = lo > m2 ? lo : m2;
+    b1 = n1;
+  }
+  if (lane == 0) { red[wv][0] = b1; red[wv][1] = b2; }
+  if (tid == 0) { s_prefix = 0; s_need = Ke; }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t x1 = 0, x2 = 0;
+    for (int w = 0; w < 4; w++) {
+      for (int t = 0; t < 2; t++) {
+        const uint64_t k = red[w][t];
+        if (k > x1) { x2 = x1; x1 = k; } else if (k > x2) { x2 = k; }
+      }
+    }
+    const bool valid = lens[r] != 0;
+    float mg = INFINITY;
+    if (NF > 1) {
+      const float s1 = row[0xFFFFFFFFu - (uint32_t)(x1 & 0xFFFFFFFFu)];
+      const float s2 = row[0xFFFFFFFFu - (uint32_t)(x2 & 0xFFFFFFFFu)];
+      mg = s1 - s2;
+    }
+    margin[r] = mg;
+    fb[r] = (valid && mg < tau) ? 1 : 0;
+  }
+  // radix select of the Ke-th largest key
+  for (int pass = 0; pass < 8; pass++) {
+    const int sh = 56 - 8 * pass;
+    const uint64_t pmask = pass ? (~0ull << (64 - 8 * pass)) : 0ull;
+    hist[tid] = 0;
+    __syncthreads();
+    const uint64_t pre = s_prefix;
+    for (uint32_t f = tid; f < NF; f += 256) {
+      const uint64_t k = score_key(row[f], f);
+      if ((k & pmask) == pre) atomicAdd(&hist[(k >> sh) & 0xFF], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t need = s_need;
+      int b = 255;
+      for (; b > 0; b--) {
+        if (hist[b] >= need) break;
+        need -= hist[b];
+      }
+      s_need = need;
+      s_prefix = pre | ((uint64_t)b << sh);
+    }
+    __syncthreads();
+  }
+  const uint64_t T = s_prefix;  // the Ke-th largest key
+  // keys >= T, compacted in increasing fragment order
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  int32_t* out = cand + (uint64_t)r * K;
+  for (uint32_t f0 = 0; f0 < NF; f0 += 256) {
+    const uint32_t f = f0 + tid;
+    const bool take = f < NF && score_key(row[f], f) >= T;
+    const uint64_t bal = __ballot(take);
+    if (lane == 0) hist[wv] = (uint32_t)__builtin_popcountll(bal);
+    __syncthreads();
+    uint32_t pos = s_base;
+    for (uint32_t w = 0; w < wv; w++) pos += hist[w];
+    pos += (uint32_t)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
+    if (take && pos < Ke) out[pos] = (int32_t)f;
+    __syncthreads();
+    if (tid == 0) s_base += hist[0] + hist[1] + hist[2] + hist[3];
+    __syncthreads();
+  }
+  for (uint32_t c = Ke + tid; c < K; c += 256) out[c] = -1;
+}
+
+// lens_out[i] = (fb[i] == want) ? lens[i] : 0
+__global__ void mask_lens_kernel(const uint32_t* __restrict__ lens, const uint8_t* __restrict__ fb,
+                                 uint8_t want, uint32_t n, uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (fb[i] == want) ? lens[i] : 0u;
+}
+
+// out[i] = fb[i] ? full[i] : cand[i]; invalid reads keep the invalid record
+__global__ void select_kernel(const maxss_top2* __restrict__ rc, const maxss_top2* __restrict__ rf,
+                              const uint8_t* __restrict__ fb, const uint32_t* __restrict__ lens,
+                              uint32_t n, maxss_top2* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = (lens[i] != 0 && fb[i]) ? rf[i] : rc[i];
+}
+
+// --------------------------------------------------------------- model
+
+struct Model {
+  int device = 0;
+  float* master = nullptr;     // [kParams] fp32
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  uint16_t* W1a = nullptr;     // [kH][kD] bf16 (W1[:, :256])
+  uint16_t* W1b = nullptr;     // [kH][kD] bf16 (W1[:, 256:])
+  float* w2f = nullptr;        // [kH] w2 rounded to bf16, as fp32
+  uint32_t step = 0;
+  // training scratch, grown on demand
+  uint32_t cap_reads = 0;
+  EncodedReads er;
+  uint16_t* rprof = nullptr;   // [cap][2][kD]
+  float* Ar = nullptr;         // [cap][kH]
+  float* Bc = nullptr;         // [cap*kCand][kH]
+  float* dy = nullptr;         // [cap*kCand]
+  float* lossv = nullptr;      // [cap]
+  uint16_t* dH = nullptr;      // [cap*kCand][kH] bf16
+  uint16_t* dA = nullptr;      // [cap][kH] bf16
+  float* part = nullptr;       // [cap][2*kH + 1] per-read dw2, db1, db2
+  float* grad = nullptr;       // [kParams]
+  int32_t* rsel = nullptr;     // [cap] profile row per read (2*b + strand)
+  // fragment profiles of the last index used (bf16, [NF][kD])
+  const Index* fp_ix = nullptr;
+  uint16_t* fprof = nullptr;
+};
+
+// bf16 shadows of W1 (split) and w2 from the fp32 master.
+__global__ void shadow_kernel(const float* __restrict__ master, uint16_t* __restrict__ W1a,
+                              uint16_t* __restrict__ W1b, float* __restrict__ w2f) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kW1) {
+    const uint32_t k = i / (2 * kD), j = i - k * 2 * kD;
+    const uint16_t b = f2bf(master[i]);
+    if (j < kD) W1a[k * kD + j] = b; else W1b[k * kD + (j - kD)] = b;
+  } else if (i < kW1 + kH) {
+    // b1 stays fp32 in the master
+  } else if (i < kW1 + 2 * kH) {
+    w2f[i - kW1 - kH] = bf2f(f2bf(master[i]));
+  }
+}
+
+static maxss_status refresh_shadow(Model* m, hipStream_t st) {
+  shadow_kernel<<<(kParams + 255) / 256, 256, 0, st>>>(m->master, m->W1a, m->W1b, m->w2f);
+  return check_hip(hipGetLastError(), "shadow_kernel");
+}
+
+static maxss_status ensure_fprof(Model* m, const Index* ix, hipStream_t st) {
+  if (m->fp_ix == ix && m->fprof) return MAXSS_OK;
+  if (m->fprof) (void)hipFree(m->fprof);
+  m->fprof = nullptr;
+  m->fp_ix = nullptr;
+  maxss_status s;
+  if ((s = check_hip(hipMalloc((void**)&m->fprof, sizeof(uint16_t) * (size_t)ix->NF * kD),
+                     "alloc fragment profiles")))
+    return s;
+  profile_kernel<<<(ix->NF + 3) / 4, 256, 0, st>>>(nullptr, nullptr, 0, 0, ix->codes, ix->F, ix->NF,
+                                                    m->fprof, nullptr);
+  if ((s = check_hip(hipGetLastError(), "profile_kernel"))) return s;
+  m->fp_ix = ix;
+  return MAXSS_OK;
+}
+
+// ---------------------------------------------------------- training
+
+// Forward + loss per read (one 256-thread block): 4 threads per candidate
+// compute y_c = w2 . ReLU(A[b] + Bc[b,c]) + b2; one wave takes the softmax
+// over the 64 candidates (label at 0): loss_b and dy = (p - onehot) / nb.
+__global__ __launch_bounds__(256) void train_fwd_kernel(const float* __restrict__ Ar,
+                                                        const float* __restrict__ Bc,
+                                                        const float* __restrict__ w2, float b2,
+                                                        uint32_t nb, float* __restrict__ dy,
+                                                        float* __restrict__ lossv) {
+  __shared__ float ys[kCand];
+  const uint32_t b = blockIdx.x, tid = threadIdx.x;
+  const uint32_t c = tid >> 2, q = tid & 3;
+  const float* a = Ar + (uint64_t)b * kH;
+  const float* bc = Bc + ((uint64_t)b * kCand + c) * kH;
+  float s = 0.f;
+  for (int k = q * 64; k < q * 64 + 64; k++) s = fmaf(w2[k], fmaxf(a[k] + bc[k], 0.f), s);
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  if (q == 0) ys[c] = s + b2;
+  __syncthreads();
+  if (tid < 64) {
+    const float y = ys[tid];
+    float mx = y;
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    float e = expf(y - mx), se = e;
+    for (int o = 32; o > 0; o >>= 1) se += __shfl_xor(se, o, 64);
+    const float lse = mx + logf(se);
+    dy[(uint64_t)b * kCand + tid] = (e / se - (tid == 0 ? 1.f : 0.f)) / (float)nb;
+    if (tid == 0) lossv[b] = lse - y;
+  }
+}
+
+// Backward per read (one block, thread = hidden unit k): dH[b,c,k] =
+// dy_c w2[k] [pre > 0] (bf16, for dW1b), dA[b,k] = sum_c dH (bf16, for dW1a),
+// and this read's partial sums of dw2 (sum_c dy_c h_c), db1 and db2.
+__global__ __launch_bounds__(256) void train_bwd_kernel(const float* __restrict__ Ar,
+                                                        const float* __restrict__ Bc,
+                                                        const float* __restrict__ w2,
+                                                        const float* __restrict__ dy,
+                                                        uint16_t* __restrict__ dH,
+                                                        uint16_t* __restrict__ dA,
+                                                        float* __restrict__ part) {
+  const uint32_t b = blockIdx.x, k = threadIdx.x;
+  const float a = Ar[(uint64_t)b * kH + k];
+  const float wk = w2[k];
+  float sa = 0.f, sw = 0.f;
+  for (int c = 0; c < kCand; c++) {
+    const uint64_t p = (uint64_t)b * kCand + c;
+    const float pre = a + Bc[p * kH + k];
+    const float d = dy[p];
+    const float g = pre > 0.f ? d * wk : 0.f;
+    dH[p * kH + k] = f2bf(g);
+    sa += g;
+    sw = fmaf(d, fmaxf(pre, 0.f), sw);
+  }
+  dA[(uint64_t)b * kH + k] = f2bf(sa);
+  float* pr = part + (uint64_t)b * (2 * kH + 1);
+  pr[k] = sw;
+  pr[kH + k] = sa;
+  if (k == 0) {
+    float d = 0.f;
+    for (int c = 0; c < kCand; c++) d += dy[(uint64_t)b * kCand + c];
+    pr[2 * kH] = d;
+  }
+}
+
+// Deterministic reduction of the per-read partials into the gradient
+// (dw2, db1, db2) and of the per-read losses into the mean loss.
+__global__ __launch_bounds__(256) void train_reduce_kernel(const float* __restrict__ part,
+                                                           const float* __restrict__ lossv,
+                                                           uint32_t nb, float* __restrict__ grad,
+                                                           float* __restrict__ loss) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 2*kH
+  if (k < 2 * kH + 1) {
+    float s = 0.f;
+    for (uint32_t b = 0; b < nb; b++) s += part[(uint64_t)b * (2 * kH + 1) + k];
+    if (k < kH) grad[kW1 + kH + k] = s;          // dw2
+    else if (k < 2 * kH) grad[kW1 + (k - kH)] = s;  // db1
+    else grad[kParams - 1] = s;                 // db2
+  }
+  if (k == 2 * kH + 1 && loss) {
+    float s = 0.f;
+    for (uint32_t b = 0; b < nb; b++) s += lossv[b];
+    *loss = s / (float)nb;
+  }
+}
+
+// dW1 assembly: grad[k*512 + j] from dW1a (j < 256) and dW1b (j >= 256),
+// both [kH][kD] fp32 in `tmp`.
+__global__ void assemble_w1_kernel(const float* __restrict__ tmp, float* __restrict__ grad) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kW1) return;
+  const uint32_t k = i / (2 * kD), j = i - k * 2 * kD;
+  grad[i] = j < kD ? tmp[k * kD + j] : tmp[kH * kD + k * kD + (j - kD)];
+}
+
+// Adam (Kingma & Ba, 2015) on the fp32 master weights.
+__global__ void adam_kernel(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, uint32_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// row index of each read's label-strand profile: 2*b + strand[b]
+__global__ void rsel_kernel(const int8_t* __restrict__ strand, uint32_t nb, int32_t* __restrict__ rs) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) rs[b] = (int32_t)(2 * b + (strand[b] ? 1 : 0));
+}
+
+static void free_train_scratch(Model* m) {
+  void* ps[] = {m->er.sel4, m->er.codes, m->er.lens, m->rprof, m->Ar, m->Bc, m->dy, m->lossv,
+                m->dH, m->dA, m->part, m->grad, m->rsel};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  m->er = EncodedReads{};
+  m->rprof = nullptr; m->Ar = nullptr; m->Bc = nullptr; m->dy = nullptr; m->lossv = nullptr;
+  m->dH = nullptr; m->dA = nullptr; m->part = nullptr; m->grad = nullptr; m->rsel = nullptr;
+  m->cap_reads = 0;
+}
+
+static maxss_status ensure_train_scratch(Model* m, const Index* ix, uint32_t nb) {
+  if (nb <= m->cap_reads && m->er.mstride == read_stride(ix)) return MAXSS_OK;
+  free_train_scratch(m);
+  const uint32_t cap = nb;
+  maxss_status s;
+  m->er.mstride = read_stride(ix);
+  const uint64_t P = (uint64_t)cap * kCand;
+  if ((s = check_hip(hipMalloc((void**)&m->er.sel4, 4ull * (cap * 2ull * (m->er.mstride / 8) + 64)),
+                     "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->er.codes, (uint64_t)cap * m->er.mstride + 64), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->er.lens, 4ull * (cap + 1)), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->rprof, 2ull * cap * 2 * kD), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->Ar, 4ull * cap * kH), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->Bc, 4ull * P * kH), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->dy, 4ull * P), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->lossv, 4ull * cap), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->dH, 2ull * P * kH), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->dA, 2ull * cap * kH), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->part, 4ull * cap * (2 * kH + 1)), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->grad, 4ull * (kParams + 2 * kH * kD)), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->rsel, 4ull * cap), "alloc"))) {
+    free_train_scratch(m);
+    return s;
+  }
+  m->cap_reads = cap;
+  return MAXSS_OK;
+}
+
+}  // namespace maxss
+
+using namespace maxss;
+
+extern "C" maxss_status maxss_model_create(const float* params, maxss_model** out) {
+  clear_error();
+  if (!params || !out) return fail(MAXSS_EINVAL, "NULL argument");
+  Model* m = new (std::nothrow) Model();
+  if (!m) return fail(MAXSS_ENOMEM, "host allocation");
+  maxss_status s;
+  do {
+    if ((s = check_hip(hipGetDevice(&m->device), "hipGetDevice"))) break;
+    if ((s = check_hip(hipMalloc((void**)&m->master, 4ull * kParams), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->adam_m, 4ull * kParams), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->adam_v, 4ull * kParams), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->W1a, 2ull * kH * kD), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->W1b, 2ull * kH * kD), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->w2f, 4ull * kH), "alloc")))
+      break;
+    if ((s = check_hip(hipMemcpy(m->master, params, 4ull * kParams, hipMemcpyHostToDevice), "copy")) ||
+        (s = check_hip(hipMemset(m->adam_m, 0, 4ull * kParams), "memset")) ||
+        (s = check_hip(hipMemset(m->adam_v, 0, 4ull * kParams), "memset")))
+      break;
+    if ((s = refresh_shadow(m, nullptr))) break;
+    if ((s = check_hip(hipDeviceSynchronize(), "sync"))) break;
+  } while (0);
+  if (s) {
+    maxss_model_free(reinterpret_cast<maxss_model*>(m));
+    return s;
+  }
+  *out = reinterpret_cast<maxss_model*>(m);
+  return MAXSS_OK;
+}
+
+extern "C" void maxss_model_free(maxss_model* model) {
+  Model* m = reinterpret_cast<Model*>(model);
+  if (!m) return;
+  free_train_scratch(m);
+  void* ps[] = {m->master, m->adam_m, m->adam_v, m->W1a, m->W1b, m->w2f, m->fprof};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+extern "C" maxss_status maxss_model_get_params(const maxss_model* model, float* out) {
+  clear_error();
+  const Model* m = reinterpret_cast<const Model*>(model);
+  if (!m || !out) return fail(MAXSS_EINVAL, "NULL argument");
+  return check_hip(hipMemcpy(out, m->master, 4ull * kParams, hipMemcpyDeviceToHost), "copy params");
+}
+
+static const char kMagic[8] = {'M', 'A', 'X', 'S', 'S', 'M', 'L', 'P'};
+
+extern "C" maxss_status maxss_model_save(const maxss_model* model, const char* path) {
+  clear_error();
+  const Model* m = reinterpret_cast<const Model*>(model);
+  if (!m || !path) return fail(MAXSS_EINVAL, "NULL argument");
+  std::vector<float> buf(3ull * kParams);
+  maxss_status s;
+  if ((s = check_hip(hipMemcpy(buf.data(), m->master, 4ull * kParams, hipMemcpyDeviceToHost), "copy")) ||
+      (s = check_hip(hipMemcpy(buf.data() + kParams, m->adam_m, 4ull * kParams, hipMemcpyDeviceToHost),
+                     "copy")) ||
+      (s = check_hip(hipMemcpy(buf.data() + 2 * kParams, m->adam_v, 4ull * kParams,
+                               hipMemcpyDeviceToHost),
+                     "copy")))
+    return s;
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(MAXSS_EINVAL, "cannot open %s for writing", path);
+  const uint32_t hdr[3] = {1u, m->step, kParams};  // format version, step, parameter count
+  bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(hdr, 4, 3, f) == 3 &&
+            fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+  ok = (fclose(f) == 0) && ok;
+  return ok ? MAXSS_OK : fail(MAXSS_EINVAL, "short write to %s", path);
+}
+
+extern "C" maxss_status maxss_model_load(const char* path, maxss_model** out) {
+  clear_error();
+  if (!path || !out) return fail(MAXSS_EINVAL, "NULL argument");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(MAXSS_EINVAL, "cannot open %s", path);
+  char mg[8];
+  uint32_t hdr[3];
+  std::vector<float> buf(3ull * kParams);
+  const bool ok = fread(mg, 1, 8, f) == 8 && memcmp(mg, kMagic, 8) == 0 && fread(hdr, 4, 3, f) == 3 &&
+                  hdr[0] == 1u && hdr[2] == kParams && fread(buf.data(), 4, buf.size(), f) == buf.size();
+  fclose(f);
+  if (!ok) return fail(MAXSS_EINVAL, "%s is not a version-1 model file", path);
+  maxss_status s = maxss_model_create(buf.data(), out);
+  if (s) return s;
+  Model* m = reinterpret_cast<Model*>(*out);
+  m->step = hdr[1];
+  if ((s = check_hip(hipMemcpy(m->adam_m, buf.data() + kParams, 4ull * kParams, hipMemcpyHostToDevice),
+                     "copy")) ||
+      (s = check_hip(hipMemcpy(m->adam_v, buf.data() + 2 * kParams, 4ull * kParams,
+                               hipMemcpyHostToDevice),
+                     "copy"))) {
+    maxss_model_free(*out);
+    *out = nullptr;
+    return s;
+  }
+  return MAXSS_OK;
+}
+
+extern "C" maxss_status maxss_profiles(const maxss_index* index, const maxss_reads* reads,
+                                       float* read_prof, float* frag_prof, void* stream) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  if (!ix || (!read_prof && !frag_prof)) return fail(MAXSS_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  maxss_status s = MAXSS_OK;
+  uint16_t* tmp = nullptr;
+  DeviceReads dr;
+  EncodedReads er;
+  const uint32_t n = (reads && read_prof) ? reads->n : 0;
+  do {
+    if (reads && read_prof) {
+      if (!reads->on_device) { s = fail(MAXSS_EINVAL, "profiles take device reads"); break; }
+      if (n) {
+        if ((s = stage_reads(reads, st, &dr))) break;
+        if ((s = alloc_encoded(ix, n, st, &er))) break;
+        if ((s = encode_reads_into(ix, dr, st, er))) break;
+        if ((s = check_hip(hipMallocAsync((void**)&tmp, 2ull * n * 2 * kD, st), "alloc"))) break;
+        profile_kernel<<<(2 * n + 3) / 4, 256, 0, st>>>(er.codes, er.lens, er.mstride, n, nullptr,
+                                                         0, 0, tmp, read_prof);
+        if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
+        (void)hipFreeAsync(tmp, st);
+        tmp = nullptr;
+      }
+    }
+    if (frag_prof) {
+      if ((s = check_hip(hipMallocAsync((void**)&tmp, 2ull * ix->NF * kD, st), "alloc"))) break;
+      profile_kernel<<<(ix->NF + 3) / 4, 256, 0, st>>>(nullptr, nullptr, 0, 0, ix->codes, ix->F,
+                                                        ix->NF, tmp, frag_prof);
+      if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
+    }
+  } while (0);
+  if (tmp) (void)hipFreeAsync(tmp, st);
+  release_encoded(&er, st);
+  release_reads(&dr, st);
+  return s;
+}
+
+// A = V_read W1a^T + b1 for rows [0, 2n): rprof [2n][kD] bf16 -> A [2n][kH]
+static maxss_status read_side(const Model* m, const uint16_t* rprof, uint32_t rows, float* A,
+                              hipStream_t st) {
+  Opnd a{rprof, kD, 1, nullptr, nullptr};
+  Opnd b{m->W1a, kD, 1, nullptr, nullptr};
+  return gemm((int)rows, kH, kD, a, b, A, kH, m->master + kW1, false, st);
+}
+
+static maxss_status frag_side(const Model* m, const uint16_t* fprof, uint32_t NF, float* B,
+                              hipStream_t st) {
+  Opnd a{fprof, kD, 1, nullptr, nullptr};
+  Opnd b{m->W1b, kD, 1, nullptr, nullptr};
+  return gemm((int)NF, kH, kD, a, b, B, kH, nullptr, false, st);
+}
+
+static float host_b2(const Model* m) {
+  float b2 = 0.f;
+  (void)hipMemcpy(&b2, m->master + kParams - 1, 4, hipMemcpyDeviceToHost);
+  return b2;
+}
+
+extern "C" maxss_status maxss_proposal_scores(const maxss_index* index, maxss_model* model,
+                                              const maxss_reads* reads, float* scores,
+                                              void* stream) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  Model* m = reinterpret_cast<Model*>(model);
+  if (!ix || !m || !reads || !scores) return fail(MAXSS_EINVAL, "NULL argument");
+  if (!reads->on_device) return fail(MAXSS_EINVAL, "scores take device reads");
+  const uint32_t n = reads->n;
+  if (n == 0) return MAXSS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  maxss_status s;
+  DeviceReads dr;
+  EncodedReads er;
+  uint16_t* rprof = nullptr;
+  float *A = nullptr, *B = nullptr;
+  do {
+    if ((s = ensure_fprof(m, ix, st))) break;
+    if ((s = stage_reads(reads, st, &dr))) break;
+    if ((s = alloc_encoded(ix, n, st, &er))) break;
+    if ((s = encode_reads_into(ix, dr, st, er))) break;
+    if ((s = check_hip(hipMallocAsync((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&A, 4ull * n * 2 * kH, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&B, 4ull * ix->NF * kH, st), "alloc")))
+      break;
+    profile_kernel<<<(2 * n + 3) / 4, 256, 0, st>>>(er.codes, er.lens, er.mstride, n, nullptr, 0, 0,
+                                                     rprof, nullptr);
+    if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
+    if ((s = read_side(m, rprof, 2 * n, A, st))) break;
+    if ((s = frag_side(m, m->fprof, ix->NF, B, st))) break;
+    const float b2 = host_b2(m);
+    dim3 grid((ix->NF + 63) / 64, (n + 31) / 32);
+    {
+      ProfScope prof("pair", st);
+      pair_kernel<<<grid, 256, 0, st>>>(A, B, m->w2f, b2, n, ix->NF, scores, ix->NF);
+    }
+    s = check_hip(hipGetLastError(), "pair_kernel");
+  } while (0);
+  if (rprof) (void)hipFreeAsync(rprof, st);
+  if (A) (void)hipFreeAsync(A, st);
+  if (B) (void)hipFreeAsync(B, st);
+  release_encoded(&er, st);
+  release_reads(&dr, st);
+  return s;
+}
+
+// Bytes of the per-batch score matrix of the proposal.
+static constexpr uint64_t kScoreBudget = 512ull << 20;
+
+// Scores, top-K candidates (cand [n][K], ascending), margins and fall-back
+// flags for n encoded reads (er).  Scratch is stream-ordered.
+static maxss_status propose_impl(const Index* ix, Model* m, const EncodedReads& er, uint32_t n,
+                                 uint32_t K, float tau, int32_t* cand, float* mg, uint8_t* fb,
+                                 hipStream_t st) {
+  maxss_status s;
+  uint16_t* rprof = nullptr;
+  float *A = nullptr, *B = nullptr, *S = nullptr;
+  do {
+    if ((s = ensure_fprof(m, ix, st))) break;
+    if ((s = check_hip(hipMallocAsync((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&A, 4ull * n * 2 * kH, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&B, 4ull * ix->NF * kH, st), "alloc")))
+      break;
+    {
+      ProfScope prof("profile", st);
+      profile_kernel<<<(2 * n + 3) / 4, 256, 0, st>>>(er.codes, er.lens, er.mstride, n, nullptr, 0,
+                                                       0, rprof, nullptr);
+    }
+    if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
+    if ((s = read_side(m, rprof, 2 * n, A, st))) break;
+    if ((s = frag_side(m, m->fprof, ix->NF, B, st))) break;
+    const float b2 = host_b2(m);
+    uint64_t batch = kScoreBudget / (4ull * ix->NF);
+    if (batch < 1) batch = 1;
+    if (batch > n) batch = n;
+    if ((s = check_hip(hipMallocAsync((void**)&S, 4ull * batch * ix->NF, st), "alloc scores"))) break;
+    for (uint32_t r0 = 0; r0 < n && !s; r0 += (uint32_t)batch) {
+      const uint32_t nb = (uint32_t)((n - r0) < batch ? (n - r0) : batch);
+      dim3 grid((ix->NF + 63) / 64, (nb + 31) / 32);
+      {
+        ProfScope prof("pair", st);
+        pair_kernel<<<grid, 256, 0, st>>>(A + (uint64_t)r0 * 2 * kH, B, m->w2f, b2, nb, ix->NF, S,
+                                          ix->NF);
+      }
+      if ((s = check_hip(hipGetLastError(), "pair_kernel"))) break;
+      {
+        ProfScope prof("topk", st);
+        topk_kernel<<<nb, 256, 0, st>>>(S, ix->NF, ix->NF, K, tau, er.lens, r0, cand, mg, fb);
+      }
+      s = check_hip(hipGetLastError(), "topk_kernel");
+    }
+  } while (0);
+  void* ps[] = {rprof, A, B, S};
+  for (void* p : ps)
+    if (p) (void)hipFreeAsync(p, st);
+  return s;
+}
+
+extern "C" maxss_status maxss_proposal_candidates(const maxss_index* index, maxss_model* model,
+                                                  const maxss_reads* reads, uint32_t K, float margin,
+                                                  int32_t* cand, float* margins, uint8_t* fell_back,
+                                                  void* stream) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  Model* m = reinterpret_cast<Model*>(model);
+  if (!ix || !m || !reads || !cand || !margins || !fell_back)
+    return fail(MAXSS_EINVAL, "NULL argument");
+  if (!reads->on_device) return fail(MAXSS_EINVAL, "the proposal path takes device reads");
+  if (K == 0 || K > 4096) return fail(MAXSS_EINVAL, "K must be in 1..4096");
+  const uint32_t n = reads->n;
+  if (n == 0) return MAXSS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  DeviceReads dr;
+  dr.seq = reads->seq;
+  dr.off = reads->offsets;
+  dr.n = n;
+  EncodedReads er;
+  maxss_status s;
+  do {
+    if ((s = alloc_encoded(ix, n, st, &er))) break;
+    if ((s = encode_reads_into(ix, dr, st, er))) break;
+    s = propose_impl(ix, m, er, n, K, margin, cand, margins, fell_back, st);
+  } while (0);
+  release_encoded(&er, st);
+  return s;
+}
+
+extern "C" maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxss_model* model,
+                                                  const maxss_reads* reads, uint32_t K,
+                                                  float margin_tau, maxss_top2* out,
+                                                  uint8_t* fell_back, void* stream) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  Model* m = reinterpret_cast<Model*>(model);
+  if (!ix || !m || !reads || !out) return fail(MAXSS_EINVAL, "NULL argument");
+  if (!reads->on_device) return fail(MAXSS_EINVAL, "the proposal path takes device reads");
+  if (K == 0 || K > 4096) return fail(MAXSS_EINVAL, "K must be in 1..4096");
+  const uint32_t n = reads->n;
+  if (n == 0) return MAXSS_OK;
+  if (!reads->seq || !reads->offsets) return fail(MAXSS_EINVAL, "NULL reads");
+  hipStream_t st = (hipStream_t)stream;
+  maxss_status s;
+  DeviceReads dr;
+  dr.seq = reads->seq;
+  dr.off = reads->offsets;
+  dr.n = n;
+  ScanWork wc, wf;
+  float* mg = nullptr;
+  int32_t* cand = nullptr;
+  uint8_t* fb = nullptr;
+  uint32_t *lens_c = nullptr, *lens_f = nullptr;
+  maxss_top2 *oc = nullptr, *of = nullptr;
+  const uint32_t Kc = K < ix->NF ? K : ix->NF;
+  do {
+    if ((s = alloc_scan_work(ix, n, scan_partial_entries(ix, n, nullptr), true, st, &wf))) break;
+    if ((s = encode_reads_into(ix, dr, st, wf.er))) break;
+    if ((s = check_hip(hipMallocAsync((void**)&cand, 4ull * n * K, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&mg, 4ull * n, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&fb, n, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&lens_c, 4ull * n, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&lens_f, 4ull * n, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&oc, sizeof(maxss_top2) * n, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&of, sizeof(maxss_top2) * n, st), "alloc")))
+      break;
+    if ((s = propose_impl(ix, m, wf.er, n, K, margin_tau, cand, mg, fb, st))) break;
+    mask_lens_kernel<<<(n + 255) / 256, 256, 0, st>>>(wf.er.lens, fb, 0, n, lens_c);
+    mask_lens_kernel<<<(n + 255) / 256, 256, 0, st>>>(wf.er.lens, fb, 1, n, lens_f);
+    if ((s = check_hip(hipGetLastError(), "mask_lens_kernel"))) break;
+    // candidate scan of the reads that kept their proposal
+    if ((s = alloc_scan_work(ix, n, (uint64_t)n * (Kc < 16 ? Kc : 16), true, st, &wc))) break;
+    if ((s = candidate_scan(ix, wf.er, lens_c, n, cand, K, Kc, oc, wc, st))) break;
+    // full scan of the reads that fell back
+    if ((s = scan_pipeline_lens(ix, wf.er, lens_f, n, of, wf, st))) break;
+    select_kernel<<<(n + 255) / 256, 256, 0, st>>>(oc, of, fb, wf.er.lens, n, out);
+    if ((s = check_hip(hipGetLastError(), "select_kernel"))) break;
+    if (fell_back &&
+        (s = check_hip(hipMemcpyAsync(fell_back, fb, n, hipMemcpyDeviceToDevice, st), "copy fb")))
+      break;
+  } while (0);
+  void* ps[] = {mg, cand, fb, lens_c, lens_f, oc, of};
+  for (void* p : ps)
+    if (p) (void)hipFreeAsync(p, st);
+  release_scan_work(&wc, true, st);
+  release_scan_work(&wf, true, st);
+  return s;
+}
+
+extern "C" maxss_status maxss_model_train_step(maxss_model* model, const maxss_index* index,
+                                               const maxss_reads* batch, const int32_t* cand,
+                                               const int8_t* strand, float lr, float* loss,
+                                               float* grad_out, void* stream) {
+  clear_error();
+  Model* m = reinterpret_cast<Model*>(model);
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  if (!m || !ix || !batch || !cand || !strand) return fail(MAXSS_EINVAL, "NULL argument");
+  if (!batch->on_device) return fail(MAXSS_EINVAL, "training takes device reads");
+  const uint32_t nb = batch->n;
+  if (nb == 0) return fail(MAXSS_EINVAL, "empty batch");
+  hipStream_t st = (hipStream_t)stream;
+  maxss_status s;
+  DeviceReads dr;
+  dr.seq = batch->seq;
+  dr.off = batch->offsets;
+  dr.n = nb;
+  if ((s = ensure_fprof(m, ix, st))) return s;
+  if ((s = ensure_train_scratch(m, ix, nb))) return s;
+  if ((s = encode_reads_into(ix, dr, st, m->er))) return s;
+  profile_kernel<<<(2 * nb + 3) / 4, 256, 0, st>>>(m->er.codes, m->er.lens, m->er.mstride, nb,
+                                                    nullptr, 0, 0, m->rprof, nullptr);
+  rsel_kernel<<<(nb + 255) / 256, 256, 0, st>>>(strand, nb, m->rsel);
+  if ((s = check_hip(hipGetLastError(), "profile/rsel"))) return s;
+  const uint32_t P = nb * kCand;
+  // forward: A = Vr W1a^T + b1 (label strand rows), Bc = Vc W1b^T
+  {
+    Opnd a{m->rprof, kD, 1, m->rsel, nullptr};
+    Opnd b{m->W1a, kD, 1, nullptr, nullptr};
+    if ((s = gemm((int)nb, kH, kD, a, b, m->Ar, kH, m->master + kW1, false, st))) return s;
+  }
+  {
+    Opnd a{m->fprof, kD, 1, cand, nullptr};
+    Opnd b{m->W1b, kD, 1, nullptr, nullptr};
+    if ((s = gemm((int)P, kH, kD, a, b, m->Bc, kH, nullptr, false, st))) return s;
+  }
+  const float b2 = host_b2(m);
+  train_fwd_kernel<<<nb, 256, 0, st>>>(m->Ar, m->Bc, m->w2f, b2, nb, m->dy, m->lossv);
+  train_bwd_kernel<<<nb, kH, 0, st>>>(m->Ar, m->Bc, m->w2f, m->dy, m->dH, m->dA, m->part);
+  if ((s = check_hip(hipGetLastError(), "train fwd/bwd"))) return s;
+  float* tmp = m->grad + kParams;  // [2][kH][kD] fp32 for dW1a, dW1b
+  {
+    // dW1a[k][j] = sum_b dA[b][k] Vr[rsel[b]][j]
+    Opnd a{m->dA, 1, kH, nullptr, nullptr};
+    Opnd b{m->rprof, 1, kD, nullptr, m->rsel};
+    if ((s = gemm(kH, kD, (int)nb, a, b, tmp, kD, nullptr, false, st))) return s;
+  }
+  {
+    // dW1b[k][j] = sum_p dH[p][k] Vf[cand[p]][j]
+    Opnd a{m->dH, 1, kH, nullptr, nullptr};
+    Opnd b{m->fprof, 1, kD, nullptr, cand};
+    if ((s = gemm(kH, kD, (int)P, a, b, tmp + kH * kD, kD, nullptr, false, st))) return s;
+  }
+  assemble_w1_kernel<<<(kW1 + 255) / 256, 256, 0, st>>>(tmp, m->grad);
+  train_reduce_kernel<<<(2 * kH + 2 + 255) / 256, 256, 0, st>>>(m->part, m->lossv, nb, m->grad, loss);
+  if ((s = check_hip(hipGetLastError(), "train reduce"))) return s;
+  if (grad_out &&
+      (s = check_hip(hipMemcpyAsync(grad_out, m->grad, 4ull * kParams, hipMemcpyDeviceToDevice, st),
+                     "copy grad")))
+    return s;
+  if (lr > 0.f) {
+    m->step++;
+    const float b1c = 1.f - powf(0.9f, (float)m->step), b2c = 1.f - powf(0.999f, (float)m->step);
+    adam_kernel<<<(kParams + 255) / 256, 256, 0, st>>>(m->master, m->adam_m, m->adam_v, m->grad,
+                                                       kParams, lr, 0.9f, 0.999f, 1e-8f, b1c, b2c);
+    if ((s = check_hip(hipGetLastError(), "adam_kernel"))) return s;
+    if ((s = refresh_shadow(m, st))) return s;
+  }
+  return MAXSS_OK;
+}

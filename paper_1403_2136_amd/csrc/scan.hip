@@ -86,6 +86,9 @@ struct ScanArgs {
   int4* partial;
   uint32_t nstrands;
   uint32_t mp_max;  // largest padded read length of the call
+  const int32_t* cand;  // NULL, or per read K candidate fragments (ascending)
+  uint32_t K;
+  uint32_t nfe;         // fragments (or candidates) each tile iterates
 };
 
 template <int NP>
@@ -142,11 +145,37 @@ __device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lba
   }
 }
 
+// One NP-step block: steps kb..kb+NP-1 use window words first[0..NP) (words
+// kb..kb+NP-1 of the lane) and second[0..NP) (words kb+NP..kb+2NP-1).
+// first[t] is last read at step t, so right after step t it is reloaded with
+// word kb+2NP+t: the block after next finds it there as its `second` half.
+template <int NP>
+__device__ inline void kadane_block(uint32_t (&first)[NP], const uint32_t (&second)[NP],
+                                    const uint32_t* __restrict__ lw, const uint32_t (&cc)[NP / 8],
+                                    uint64_t xpool, uint64_t dpool, s16x2 (&H)[NP],
+                                    s16x2 (&B)[NP]) {
+#pragma unroll
+  for (int t = 0; t < NP; t++) {
+    const uint32_t c = (cc[t >> 3] >> (4 * (t & 7))) & 15u;
+    const uint64_t pool = xpool ^ (dpool << (c << 3));
+    const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
+#pragma unroll
+    for (int j = 0; j < NP; j++) {
+      const uint32_t w = (j + t < NP) ? first[j + t] : second[j + t - NP];
+      uint32_t sg = __builtin_amdgcn_perm(phi, plo, w);
+      H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
+    }
+#pragma unroll
+    for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
+    first[t] = lw[t];
+  }
+}
+
 // Kadane over one read strand of length m for this lane's NP offset pairs.
 // lc: the strand's 4-bit codes in LDS.  Full NP-step blocks first (window in
-// registers, refilled from LDS one block ahead), then the last m % NP steps
-// as unrolled sub-blocks of 8/4/2/1 steps, so no padding step is computed.
-// Returns the lane's per-pair maxima (biased by -32768) in B.
+// two register halves that swap roles every block), then the last m % NP
+// steps as unrolled sub-blocks of 8/4/2/1 steps, so no padding step is
+// computed.  Returns the lane's per-pair maxima (biased by -32768) in B.
 template <int NP>
 __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t lane,
                                     const uint32_t* __restrict__ lc, uint32_t m,
@@ -162,49 +191,38 @@ __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t l
   const uint32_t lbase = lane * (NP + 1);
   const uint32_t mfull = m / NP * NP;
   if (mfull) {
-    uint32_t win[2 * NP];
-    uint32_t nxt[NP];
+    uint32_t wA[NP], wB[NP];
     uint32_t cn[CW];
 #pragma unroll
     for (int i = 0; i < NP; i++) {
-      win[i] = win_word<NP>(lds, lbase, i);
-      nxt[i] = win_word<NP>(lds, lbase, NP + i);
+      wA[i] = win_word<NP>(lds, lbase, i);
+      wB[i] = win_word<NP>(lds, lbase, NP + i);
     }
 #pragma unroll
     for (int i = 0; i < CW; i++) cn[i] = __builtin_amdgcn_readfirstlane(lc[i]);
     // pb = kb + kb/NP: slot offset of word kb; word kb + 2*NP + i (i < NP)
-    // sits at pb + 2*(NP+1) + i
-    uint32_t pb = 0;
-    for (uint32_t kb = 0; kb < mfull; kb += NP, pb += NP + 1) {
+    // sits at pb + 2*(NP+1) + i.  Reloads stay inside the staged window
+    // (lane*NP + m + 2*NP words), code prefetches inside m/8 + NP/8 + 1.
+    uint32_t pb = 0, kb = 0;
+    for (; kb + 2 * NP <= mfull; kb += 2 * NP, pb += 2 * (NP + 1)) {
       uint32_t cc[CW];
 #pragma unroll
       for (int i = 0; i < CW; i++) cc[i] = cn[i];
 #pragma unroll
-      for (int i = 0; i < NP; i++) win[NP + i] = nxt[i];
-      // prefetch the next block's window words and code words (inside the
-      // staged ranges: the window covers lane*NP + m + 2*NP words, the codes
-      // m/8 + NP/8 + 1 words)
-      const uint32_t* lw = lds + lbase + pb + 2 * (NP + 1);
+      for (int i = 0; i < CW; i++) cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + NP) / 8 + i]);
+      kadane_block<NP>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, xpool, dpool, H, B);
 #pragma unroll
-      for (int i = 0; i < NP; i++) nxt[i] = lw[i];
+      for (int i = 0; i < CW; i++) cc[i] = cn[i];
 #pragma unroll
       for (int i = 0; i < CW; i++)
-        cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + NP) / 8 + i]);
+        cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + 2 * NP) / 8 + i]);
+      kadane_block<NP>(wB, wA, lds + lbase + pb + 3 * (NP + 1), cc, xpool, dpool, H, B);
+    }
+    if (kb < mfull) {  // one block left
+      uint32_t cc[CW];
 #pragma unroll
-      for (int t = 0; t < NP; t++) {
-        const uint32_t c = (cc[t >> 3] >> (4 * (t & 7))) & 15u;
-        const uint64_t pool = xpool ^ (dpool << (c << 3));
-        const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
-#pragma unroll
-        for (int j = 0; j < NP; j++) {
-          uint32_t sg = __builtin_amdgcn_perm(phi, plo, win[j + t]);
-          H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
-        }
-#pragma unroll
-        for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
-      }
-#pragma unroll
-      for (int i = 0; i < NP; i++) win[i] = win[NP + i];
+      for (int i = 0; i < CW; i++) cc[i] = cn[i];
+      kadane_block<NP>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, xpool, dpool, H, B);
     }
   }
   const uint32_t rem = m - mfull;
@@ -247,8 +265,12 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
     const uint32_t my_mp = (my_len + NP - 1) / NP * NP;
     const uint32_t mp_tile = (uint32_t)wave_max_i32((int)my_mp);
     const uint32_t nwords = staged_words<NP>(mp_tile);
+    if (mp_tile == 0) continue;  // a tile of skipped reads (length 0)
     int t1s = -1, t1f = -1, t2s = -1, t2f = -1;
-    const uint32_t f0 = chunk * a.C, f1 = min(a.NF, f0 + a.C);
+    const uint32_t f0 = chunk * a.C, f1 = min(a.nfe, f0 + a.C);
+    // candidate mode: one read per tile, fragments from its sorted list
+    const int32_t* clist =
+        a.cand ? a.cand + (uint64_t)__builtin_amdgcn_readfirstlane(my_read) * a.K : nullptr;
     // the tile's read codes, both strands, into LDS (N-padded to cw words)
     __syncthreads();
     for (uint32_t idx = lane; idx < rcount * 2 * a.cw; idx += 64) {
@@ -257,7 +279,8 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
       const uint32_t rid = a.order[rbase + r];
       lcodes[idx] = wd < a.cwg ? a.sel4[((uint64_t)rid * 2 + s) * a.cwg + wd] : 0x44444444u;
     }
-    for (uint32_t f = f0; f < f1; f++) {
+    for (uint32_t fi = f0; fi < f1; fi++) {
+      const uint32_t f = clist ? (uint32_t)clist[fi] : fi;
       int fv = -1;  // lane r: value of fragment f for read r
       for (uint32_t seg = 0; seg < a.nseg; seg++) {
         const uint64_t base = (uint64_t)f * a.F + (uint64_t)seg * S;
@@ -649,16 +672,34 @@ void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st) {
   w->partial = nullptr;
 }
 
-maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* dout,
-                           const ScanWork& w, const TileOverride* force, hipStream_t st) {
-  const uint32_t n = r.n;
-  if (n == 0) return MAXSS_OK;
+// Sort (by `lens`), scan, merge and re-scan for n encoded reads.  Reads with
+// lens[i] == 0 are skipped and get an invalid record.  cand != NULL: scan
+// only each read's Kc first candidates (K per read, ascending), one read per
+// tile.
+static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uint32_t* lens,
+                              uint32_t n, maxss_top2* dout, const ScanWork& w,
+                              const TileOverride* force, const int32_t* cand, uint32_t K,
+                              uint32_t Kc, hipStream_t st) {
   maxss_status s;
   const uint32_t nstrands = (ix->p.flags & MAXSS_ONE_STRAND) ? 1u : 2u;
-  const EncodedReads& er = w.er;
-  if ((s = encode_reads_into(ix, r, st, er))) return s;
   const uint32_t mstride = er.mstride;
   Tiles t = choose_tiles(ix, n, mstride, force, w.partial_cap);
+  if (cand) {
+    // one read per tile; enough candidate chunks to fill the resident waves
+    t.R = 1;
+    const size_t per_read = (size_t)2 * t.cw * 4u;
+    t.lds = (size_t)t.win_slots * 4u + per_read;
+    const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.lds);
+    t.ntiles = n;
+    uint64_t want = (8ull * resident + n - 1) / n;
+    if (want < 1) want = 1;
+    if (want > Kc) want = Kc;
+    if (want * n > w.partial_cap) want = w.partial_cap / n ? w.partial_cap / n : 1;
+    t.C = (uint32_t)((Kc + want - 1) / want);
+    t.nchunks = (Kc + t.C - 1) / t.C;
+    const uint64_t total = (uint64_t)t.ntiles * t.nchunks;
+    t.grid = (uint32_t)(total < resident ? total : resident);
+  }
   if ((uint64_t)n * t.nchunks > w.partial_cap)
     return fail(MAXSS_ESTATE, "partial buffer too small (%llu < %llu)",
                 (unsigned long long)w.partial_cap, (unsigned long long)n * t.nchunks);
@@ -670,9 +711,9 @@ maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* do
   // reads ordered by length, longest first
   const uint32_t nb = ix->p.max_read_len + 1;
   fill_u32_kernel<<<(nb + 255) / 256, 256, 0, st>>>(w.hist, 0u, nb);
-  len_hist_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, w.hist);
+  len_hist_kernel<<<(n + 255) / 256, 256, 0, st>>>(lens, n, w.hist);
   len_starts_kernel<<<1, 1024, 0, st>>>(w.hist, nb);
-  len_scatter_kernel<<<(n + 255) / 256, 256, 0, st>>>(er.lens, n, w.hist, w.order);
+  len_scatter_kernel<<<(n + 255) / 256, 256, 0, st>>>(lens, n, w.hist, w.order);
   fill_u32_kernel<<<1, 64, 0, st>>>(w.ctr, 0u, 1u);
   if ((s = check_hip(hipGetLastError(), "length sort"))) return s;
   ScanArgs a{};
@@ -680,26 +721,49 @@ maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* do
   a.F = ix->F; a.NF = ix->NF; a.nseg = t.nseg;
   a.sel4 = er.sel4; a.cwg = mstride / 8; a.cw = t.cw; a.win_slots = t.win_slots;
   a.xpool = xpool; a.dpool = (uint64_t)(M8 ^ X8);
-  a.lens = er.lens; a.order = w.order; a.n = n;
+  a.lens = lens; a.order = w.order; a.n = n;
   a.R = t.R; a.ntiles = t.ntiles; a.C = t.C; a.nchunks = t.nchunks;
   a.total_work = t.ntiles * t.nchunks; a.work_ctr = w.ctr; a.partial = w.partial;
   a.nstrands = nstrands; a.mp_max = mstride;
+  a.cand = cand; a.K = K; a.nfe = cand ? Kc : ix->NF;
   if (t.NP == 8) s = launch_scan<8>(a, t.grid, t.lds, st);
   else if (t.NP == 16) s = launch_scan<16>(a, t.grid, t.lds, st);
   else s = launch_scan<32>(a, t.grid, t.lds, st);
   if (s) return s;
   {
     ProfScope prof("merge", st);
-    merge_kernel<<<(n + 255) / 256, 256, 0, st>>>(w.partial, t.nchunks, er.lens, n, dout);
+    merge_kernel<<<(n + 255) / 256, 256, 0, st>>>(w.partial, t.nchunks, lens, n, dout);
   }
   if ((s = check_hip(hipGetLastError(), "merge_kernel"))) return s;
   const size_t rl = (size_t)ix->F + 3 * (size_t)mstride + 16;
   {
     ProfScope prof("rescan", st);
-    rescan_kernel<<<dim3(n, 2), 256, rl, st>>>(ix->codes, ix->F, er.codes, er.lens, mstride,
+    rescan_kernel<<<dim3(n, 2), 256, rl, st>>>(ix->codes, ix->F, er.codes, lens, mstride,
                                                ix->p.match, ix->p.mismatch, nstrands, n, dout);
   }
   return check_hip(hipGetLastError(), "rescan_kernel");
+}
+
+maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* dout,
+                           const ScanWork& w, const TileOverride* force, hipStream_t st) {
+  const uint32_t n = r.n;
+  if (n == 0) return MAXSS_OK;
+  maxss_status s;
+  if ((s = encode_reads_into(ix, r, st, w.er))) return s;
+  return scan_core(ix, w.er, w.er.lens, n, dout, w, force, nullptr, 0, 0, st);
+}
+
+maxss_status scan_pipeline_lens(const Index* ix, const EncodedReads& er, const uint32_t* lens,
+                                uint32_t n, maxss_top2* dout, const ScanWork& w, hipStream_t st) {
+  if (n == 0) return MAXSS_OK;
+  return scan_core(ix, er, lens, n, dout, w, nullptr, nullptr, 0, 0, st);
+}
+
+maxss_status candidate_scan(const Index* ix, const EncodedReads& er, const uint32_t* lens,
+                            uint32_t n, const int32_t* cand, uint32_t K, uint32_t Kc,
+                            maxss_top2* dout, const ScanWork& w, hipStream_t st) {
+  if (n == 0) return MAXSS_OK;
+  return scan_core(ix, er, lens, n, dout, w, nullptr, cand, K, Kc, st);
 }
 
 }  // namespace maxss

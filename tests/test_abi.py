@@ -80,3 +80,12 @@ def test_null_arguments(L):
     assert L.maxss_index_info(None, None, None, None) == mx.MAXSS_EINVAL
     L.maxss_index_free(None)   # no-op
     assert b"NULL" in L.maxss_last_error()
+
+
+def test_host_offsets_checked_against_buffer(L):
+    with pytest.raises(ValueError):
+        mx._host_csr(b"ACGT", [0, 5])
+    with pytest.raises(ValueError):
+        mx._host_csr(b"ACGT", [0, 3, 2])
+    s, off = mx._host_csr(b"ACGT", [0, 2, 4])
+    assert s.size == 4 and off.tolist() == [0, 2, 4]
