@@ -28,6 +28,25 @@ INT16_PACKED_OPS = CU * SIMD_LANES * CLOCK * 2   # 16-bit lane ops/s with packed
 OPS_PER_CELL = 3   # substitution-score select, saturating add (Kadane's add+clamp), running max
 
 
+def recorded_traffic(workload: str):
+    """HBM bytes per scan launch from the committed counter summary of this
+    workload, or None when there is none or the scan kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "scan_kernel_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    want, traffic = None, None
+    for line in open(path):
+        if line.startswith("scan sources sha256:"):
+            want = line.split(":", 1)[1].split()
+        elif line.startswith("traffic bytes per launch:"):
+            traffic = int(line.split(":", 1)[1])
+    have = [hashlib.sha256(open(os.path.join(ROOT, "paper_1403_2136_amd", "csrc", f), "rb")
+                           .read()).hexdigest() for f in ("scan.hip", "internal.h")]
+    return traffic if want == have else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -90,6 +109,11 @@ def proposal_leg(ix, w, seq, off, top_full, stream, args):
     t_train = time.time() - t1
     c, mg, fb = P.candidates(ix, model, dva, args.K)
     tau = P.choose_margin(c, mg, lva, 0.995)
+    untrained = mx.Model(gen.mlp_init(43))
+    cu, _, _ = P.candidates(ix, untrained, dva, args.K)
+    ce = {"trained": P.heldout_loss(P.scores(ix, model, dva), lva, 45),
+          "untrained": P.heldout_loss(P.scores(ix, untrained, dva), lva, 45)}
+    untrained.close()
     log("proposal: labels %.1fs, %d steps in %.1fs (loss %.3f -> %.3f), val recall@%d %.4f, "
         "tau %.4f" % (t_label, args.train_steps, t_train, losses[0][1], losses[-1][1], args.K,
                       P.recall(c, lva).mean(), tau))
@@ -116,7 +140,9 @@ def proposal_leg(ix, w, seq, off, top_full, stream, args):
            "fallback_rate": round(float(fbt.cpu().numpy().mean()), 4), "K": args.K,
            "tau": round(tau, 5), "train_reads": trn.n, "train_steps": args.train_steps,
            "train_s": round(t_train, 2), "label_s": round(t_label, 2),
-           "val_recall_at_K": round(float(P.recall(c, lva).mean()), 5)}
+           "val_recall_at_K": round(float(P.recall(c, lva).mean()), 5),
+           "val_recall_at_K_untrained": round(float(P.recall(cu, lva).mean()), 5),
+           "val_ce": {k: round(v, 4) for k, v in ce.items()}}
     log("proposal: %s" % res)
     model.close()
     return res
@@ -265,7 +291,7 @@ def main():
             "peak": round(peak, 2),
             "unit": "Tops/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": recorded_traffic(w.name),
         },
     }
     if tune is not None:

@@ -410,23 +410,22 @@ def sample_negatives(seed: int, step: int, labels: np.ndarray, second: np.ndarra
     others = max(NF - 1, 1)
     x = st.integers(0, others, B * D).reshape(B, D)
     x = x + (x >= labels[:, None])                        # skip the label
-    x = np.sort(x, axis=1)
-    dup = np.zeros_like(x, dtype=bool)
-    dup[:, 1:] = x[:, 1:] == x[:, :-1]
-    x = np.where(dup, np.iinfo(np.int64).max, x)
-    x = np.sort(x, axis=1)                                # distinct values first
     has2 = (second >= 0) & (second < NF) & (second != labels)
+    # a draw is dropped when it repeats an earlier draw of its row or equals
+    # the `second` already placed first; survivors keep their draw order
+    order = np.argsort(x, axis=1, kind="stable")
+    xs = np.take_along_axis(x, order, axis=1)
+    drop_s = np.zeros_like(xs, dtype=bool)
+    drop_s[:, 1:] = xs[:, 1:] == xs[:, :-1]
+    drop = np.zeros_like(drop_s)
+    np.put_along_axis(drop, order, drop_s, axis=1)
+    drop |= (x == second[:, None]) & has2[:, None]
+    pos = np.arange(D)[None, :]
+    keep = np.argsort(np.where(drop, D + pos, pos), axis=1, kind="stable")
+    x = np.where(np.take_along_axis(drop, keep, axis=1), NF, np.take_along_axis(x, keep, axis=1))
     out = np.empty((B, n_neg), dtype=np.int64)
     out[:, 0] = np.where(has2, second, x[:, 0])
-    rest = x[:, :n_neg]
-    # drop `second` from the uniform draws where it is used, keep order
-    keep = ~((rest == second[:, None]) & has2[:, None])
-    for b in np.nonzero(~keep.all(axis=1))[0]:            # rare: a draw equals `second`
-        row = rest[b][keep[b]]
-        rest[b, :row.size] = row
-        rest[b, row.size:] = x[b, n_neg]
-    start = np.where(has2, 1, 1)
-    out[:, 1:] = np.where(has2[:, None], rest[:, :n_neg - 1], rest[:, 1:n_neg])
+    out[:, 1:] = np.where(has2[:, None], x[:, :n_neg - 1], x[:, 1:n_neg])
     bad = out >= NF                                        # tiny genomes: too few fragments
     if bad.any():
         for b in np.nonzero(bad.any(axis=1))[0]:

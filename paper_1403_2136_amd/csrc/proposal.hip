@@ -543,6 +543,15 @@ __global__ void adam_kernel(float* __restrict__ th, float* __restrict__ m, float
   th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+__global__ void fill_flag_kernel(uint32_t* flag) { *flag = 0u; }
+
+// flag |= 1 if any of the n fragment ids is outside [0, NF)
+__global__ void check_ids_kernel(const int32_t* __restrict__ ids, uint32_t n, uint32_t NF,
+                                 uint32_t* __restrict__ flag) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (ids[i] < 0 || (uint32_t)ids[i] >= NF)) atomicOr(flag, 1u);
+}
+
 // row index of each read's label-strand profile: 2*b + strand[b]
 __global__ void rsel_kernel(const int8_t* __restrict__ strand, uint32_t nb, int32_t* __restrict__ rs) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -957,6 +966,17 @@ extern "C" maxss_status maxss_model_train_step(maxss_model* model, const maxss_i
   dr.n = nb;
   if ((s = ensure_fprof(m, ix, st))) return s;
   if ((s = ensure_train_scratch(m, ix, nb))) return s;
+  {
+    // every candidate must name a fragment of the index (they are gathered)
+    uint32_t* flag = m->rsel ? reinterpret_cast<uint32_t*>(m->lossv) : nullptr;
+    fill_flag_kernel<<<1, 1, 0, st>>>(flag);
+    check_ids_kernel<<<(nb * kCand + 255) / 256, 256, 0, st>>>(cand, nb * kCand, ix->NF, flag);
+    uint32_t h = 0;
+    if ((s = check_hip(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st), "copy flag")) ||
+        (s = check_hip(hipStreamSynchronize(st), "sync")))
+      return s;
+    if (h) return fail(MAXSS_EINVAL, "candidate fragment ids must lie in [0, %u)", ix->NF);
+  }
   if ((s = encode_reads_into(ix, dr, st, m->er))) return s;
   profile_kernel<<<(2 * nb + 3) / 4, 256, 0, st>>>(m->er.codes, m->er.lens, m->er.mstride, nb,
                                                     nullptr, 0, 0, m->rprof, nullptr);

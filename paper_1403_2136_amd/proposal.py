@@ -87,6 +87,31 @@ def candidates(index: Index, model: Model, reads: DeviceReads, K: int, tau: floa
     return cand.cpu().numpy().reshape(n, K), mg.cpu().numpy(), fb.cpu().numpy()
 
 
+def scores(index: Index, model: Model, reads: DeviceReads) -> np.ndarray:
+    """Network score of every (read, fragment), max over strands (host,
+    float32, n x NF)."""
+    torch = _torch()
+    out = torch.zeros(max(reads.n, 1) * index.NF, dtype=torch.float32, device="cuda")
+    s, o = reads.view()
+    model.scores(index, s, o, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[:reads.n * index.NF].reshape(reads.n, index.NF)
+
+
+def heldout_loss(score: np.ndarray, labels: np.ndarray, seed: int) -> float:
+    """Mean softmax cross-entropy of the label fragment against 63 negatives
+    drawn as in training, on strand-maxed scores of held-out reads."""
+    import gen
+    n, NF = score.shape
+    lab = labels["frag"][:, 0].astype(np.int64)
+    neg = gen.sample_negatives(seed, 0, lab, labels["frag"][:, 1].astype(np.int64), NF)
+    s = np.take_along_axis(score.astype(np.float64),
+                           np.concatenate([lab[:, None], neg.astype(np.int64)], axis=1), axis=1)
+    top = s.max(axis=1, keepdims=True)
+    lse = np.log(np.exp(s - top).sum(axis=1)) + top[:, 0]
+    return float((lse - s[:, 0]).mean())
+
+
 def recall(cand: np.ndarray, labels: np.ndarray) -> np.ndarray:
     """Per read: is the full scan's best fragment among the candidates."""
     return (cand == labels["frag"][:, :1]).any(axis=1)

@@ -84,3 +84,27 @@ def test_damage_raises_ct_at_five_prime_end():
     # without damage each is ~25%; C->T at rate 0.3 at the first base
     assert (first == ord("C")).mean() < 0.21 and (first == ord("T")).mean() > 0.29
     assert (last == ord("G")).mean() < 0.21 and (last == ord("A")).mean() > 0.29
+
+
+def test_negatives_distinct_unbiased_and_second_first():
+    NF, B = 2269, 4096
+    st = gen.Stream(5, "neg.test")
+    labels = st.integers(0, NF, B)
+    second = np.where(st.uniform(B) < 0.5, st.integers(0, NF, B), -1)
+    neg = gen.sample_negatives(3, 0, labels, second, NF)
+    assert neg.shape == (B, 63) and neg.dtype == np.int32
+    assert ((neg >= 0) & (neg < NF)).all()
+    assert (neg != labels[:, None]).all()
+    for b in range(B):
+        assert len(set(neg[b].tolist())) == 63
+    has2 = (second >= 0) & (second != labels)
+    assert (neg[has2, 0] == second[has2]).all()
+    # the uniform draws cover the whole id range: mean and quartiles of a
+    # uniform variable on [0, NF), within several standard errors
+    u = neg[:, 1:].ravel().astype(np.float64)
+    se = NF / np.sqrt(12 * u.size)
+    assert abs(u.mean() - (NF - 1) / 2) < 6 * se
+    assert abs((u < NF / 4).mean() - 0.25) < 0.01 and abs((u >= 3 * NF / 4).mean() - 0.25) < 0.01
+    # tiny genomes: every other fragment appears, cycled
+    small = gen.sample_negatives(3, 1, np.array([2]), np.array([-1]), 5)
+    assert sorted(set(small[0].tolist())) == [0, 1, 3, 4]
