@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK = 0
 ONE_STRAND = 1
+FAST = 2
 NW_FIT = 0
 NW_GLOBAL = 1
 
@@ -63,7 +64,7 @@ def lib():
         L.oracle_maxss_seq.argtypes = [c.c_void_p, c.c_uint32]
         L.oracle_window_score.restype = c.c_int
         L.oracle_window_score.argtypes = [c.c_char_p, c.c_uint32, c.c_char_p, c.c_uint64,
-                                          c.c_uint64, c.c_int32, c.c_int32,
+                                          c.c_uint64, c.c_int32, c.c_int32, c.c_uint32,
                                           c.POINTER(c.c_int32)]
         L.oracle_revcomp.restype = None
         L.oracle_revcomp.argtypes = [c.c_char_p, c.c_uint32, c.c_char_p]
@@ -104,10 +105,11 @@ def maxss_seq(x) -> int:
     return int(lib().oracle_maxss_seq(a.ctypes.data, a.size))
 
 
-def window_score(read, genome, p: int, M: int = 1, X: int = -1) -> int:
+def window_score(read, genome, p: int, M: int = 1, X: int = -1, step: int = 1) -> int:
+    """MaxSS of the window at p; step 2 scores every other read base (fast)."""
     r, g = _b(read), _b(genome)
     out = ctypes.c_int32()
-    st = lib().oracle_window_score(r, len(r), g, len(g), p, M, X, ctypes.byref(out))
+    st = lib().oracle_window_score(r, len(r), g, len(g), p, M, X, step, ctypes.byref(out))
     if st != OK:
         raise ValueError("oracle_window_score failed: %d" % st)
     return out.value

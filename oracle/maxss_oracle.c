@@ -47,6 +47,7 @@
 #define OR_ENOMEM (-2)
 
 #define OR_ONE_STRAND 1u  /* scan the read as given only */
+#define OR_FAST 2u        /* MaxSSmap_fast: score every other read base */
 
 /* Output record of the scan: 32 bytes, little-endian, no implicit padding. */
 typedef struct {
@@ -132,11 +133,13 @@ int32_t oracle_maxss_seq(const int32_t* x, uint32_t n) {
 
 /* MaxSS score of read q (length m, upper-case) against the genome window
  * starting at absolute position p: the maximum scoring subsequence of the
- * ungapped substitution scores subst(q[k], g[p+k]), k = 0..m-1. */
+ * ungapped substitution scores subst(q[k], g[p+k]), k = 0..m-1.  With
+ * step 2 (MaxSSmap_fast, Methods paragraph of that name) only the read
+ * positions k = 0, 2, 4, ... enter the sequence, each against g[p+k]. */
 static int32_t window_score(const char* q, uint32_t m, const char* g, uint64_t G,
-                            uint64_t p, int32_t M, int32_t X) {
+                            uint64_t p, int32_t M, int32_t X, uint32_t step) {
   int32_t H = 0, B = 0;
-  for (uint32_t k = 0; k < m; k++) {
+  for (uint32_t k = 0; k < m; k += step) {
     H = H + subst(q[k], genome_at(g, G, p + k), M, X);
     if (H < 0) H = 0;
     if (H > B) B = H;
@@ -145,11 +148,12 @@ static int32_t window_score(const char* q, uint32_t m, const char* g, uint64_t G
 }
 
 int oracle_window_score(const char* read, uint32_t m, const char* genome, uint64_t G,
-                        uint64_t p, int32_t M, int32_t X, int32_t* out) {
+                        uint64_t p, int32_t M, int32_t X, uint32_t step, int32_t* out) {
+  if (step != 1 && step != 2) return OR_EINVAL;
   char* q = normalise(read, m);
   char* g = normalise(genome, G);
   if (!q || !g) { free(q); free(g); return OR_EINVAL; }
-  *out = window_score(q, m, g, G, p, M, X);
+  *out = window_score(q, m, g, G, p, M, X, step);
   free(q); free(g);
   return OR_OK;
 }
@@ -160,7 +164,7 @@ int oracle_window_score(const char* read, uint32_t m, const char* genome, uint64
  * v[f], with representative strand s[f] and offset o[f]. */
 static void fragment_values(const char* q_fwd, const char* q_rc, uint32_t m,
                             const char* g, uint64_t G, uint32_t F, uint32_t NF,
-                            int32_t M, int32_t X, int one_strand,
+                            int32_t M, int32_t X, int one_strand, uint32_t step,
                             int32_t* v, int32_t* s_out, int32_t* o_out) {
   for (uint32_t f = 0; f < NF; f++) {
     int32_t best = -1, bs = 0, bo = 0;
@@ -168,7 +172,7 @@ static void fragment_values(const char* q_fwd, const char* q_rc, uint32_t m,
       const char* q = s == 0 ? q_fwd : q_rc;
       for (uint32_t o = 0; o < F; o++) {
         uint64_t p = (uint64_t)f * F + o;
-        int32_t sc = window_score(q, m, g, G, p, M, X);
+        int32_t sc = window_score(q, m, g, G, p, M, X, step);
         if (sc > best) { best = sc; bs = s; bo = (int32_t)o; } /* strict: keeps smallest s, o */
       }
     }
@@ -199,7 +203,7 @@ static void top_two(const int32_t* v, const int32_t* s, const int32_t* o, uint32
 typedef struct {
   const char* g; uint64_t G; uint32_t F, NF;
   const char* reads; const uint64_t* offsets; uint32_t n;
-  int32_t M, X; int one_strand;
+  int32_t M, X; int one_strand; uint32_t step;
   int tid, nthreads;
   oracle_top2* out;
   int32_t* all_v; /* optional n x NF matrix of fragment values */
@@ -218,7 +222,8 @@ static void* scan_worker(void* arg) {
     char* rc = (char*)malloc(m ? m : 1);
     if (!q || !rc) { free(q); free(rc); J->status = OR_EINVAL; break; }
     oracle_revcomp(q, m, rc);
-    fragment_values(q, rc, m, J->g, J->G, J->F, J->NF, J->M, J->X, J->one_strand, v, s, o);
+    fragment_values(q, rc, m, J->g, J->G, J->F, J->NF, J->M, J->X, J->one_strand, J->step, v,
+                    s, o);
     top_two(v, s, o, J->NF, &J->out[i]);
     if (J->all_v) memcpy(J->all_v + (uint64_t)i * J->NF, v, sizeof(int32_t) * J->NF);
     free(q); free(rc);
@@ -228,7 +233,8 @@ static void* scan_worker(void* arg) {
 }
 
 /* Full scan: top-2 record per read.  reads is a CSR concatenation (offsets has
- * n+1 entries).  all_v (may be NULL) receives the n x NF fragment values. */
+ * n+1 entries).  all_v (may be NULL) receives the n x NF fragment values.
+ * flags: OR_ONE_STRAND, OR_FAST (every other read base, per strand). */
 int oracle_scan(const char* genome, uint64_t G, uint32_t F, const char* reads,
                 const uint64_t* offsets, uint32_t n, int32_t M, int32_t X, uint32_t flags,
                 int nthreads, oracle_top2* out, int32_t* all_v) {
@@ -244,7 +250,7 @@ int oracle_scan(const char* genome, uint64_t G, uint32_t F, const char* reads,
   if (!jobs || !th) { free(g); free(jobs); free(th); return OR_ENOMEM; }
   for (int t = 0; t < nthreads; t++) {
     scan_job J = {g, G, F, NF, reads, offsets, n, M, X, (flags & OR_ONE_STRAND) != 0,
-                  t, nthreads, out, all_v, OR_OK};
+                  (flags & OR_FAST) ? 2u : 1u, t, nthreads, out, all_v, OR_OK};
     jobs[t] = J;
     pthread_create(&th[t], NULL, scan_worker, &jobs[t]);
   }

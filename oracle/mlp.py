@@ -135,10 +135,12 @@ def forward_decomposed(params, v_read: np.ndarray, v_frag: np.ndarray) -> np.nda
     return h @ w2 + b2
 
 
-def loss_and_grad(params, v_read: np.ndarray, v_cand: np.ndarray):
+def loss_and_grad(params, v_read: np.ndarray, v_cand: np.ndarray, parts: bool = False):
     """Mean softmax cross-entropy over reads.  v_read: (B, 256) profile of
     each read in its label strand; v_cand: (B, 64, 256) candidate fragment
-    profiles, label first.  Returns (loss, y (B, 64), gradient (N_PARAMS,))."""
+    profiles, label first.  Returns (loss, y (B, 64), gradient (N_PARAMS,)),
+    and with `parts` also a dict of the intermediate terms (z, pre, h, dy, dh)
+    for error analysis."""
     W1, b1, w2, b2 = unpack(params)
     Bn, C, _ = v_cand.shape
     z = np.concatenate([np.repeat(v_read[:, None, :], C, axis=1), v_cand], axis=2)
@@ -157,7 +159,10 @@ def loss_and_grad(params, v_read: np.ndarray, v_cand: np.ndarray):
     dh = np.outer(dyf, w2) * (pre > 0)
     db1 = dh.sum(axis=0)
     dW1 = dh.T @ z.reshape(Bn * C, 2 * D)
-    return loss, y, pack(dW1, db1, dw2, db2)
+    g = pack(dW1, db1, dw2, db2)
+    if parts:
+        return loss, y, g, dict(z=z.reshape(Bn * C, 2 * D), pre=pre, h=h, dy=dyf, dh=dh)
+    return loss, y, g
 
 
 class Adam:
