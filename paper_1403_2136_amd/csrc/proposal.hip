@@ -13,6 +13,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
@@ -115,11 +116,35 @@ __device__ inline uint16_t opnd_at(const Opnd& o, int r, int k) {
   return o.p[rr * o.sr + kk * o.sk];
 }
 
+// One operand's 64 x 32 slab (rows base.., k k0..) into LDS, zero outside
+// [0, lim) x [k0, kend).  Consecutive threads take consecutive elements along
+// the operand's contiguous dimension, so rows of a row-major operand and
+// columns of a transposed one are both read as whole cache lines.
+__device__ inline void stage_opnd(uint16_t (*S)[36], const Opnd& o, int base, int lim, int k0,
+                                  int kend, int tid) {
+  if (o.sr == 1) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int r = e & 63, kk = e >> 6;
+      const int gr = base + r, gk = k0 + kk;
+      S[r][kk] = (gr < lim && gk < kend) ? opnd_at(o, gr, gk) : (uint16_t)0;
+    }
+  } else {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int r = e >> 5, kk = e & 31;
+      const int gr = base + r, gk = k0 + kk;
+      S[r][kk] = (gr < lim && gk < kend) ? opnd_at(o, gr, gk) : (uint16_t)0;
+    }
+  }
+}
+
 // C[i][j] (+)= sum_k A(i,k) B(j,k) (+ bias[j]), fp32 out (ldc), bf16 in.
 // 256 threads, 64x64 output tile, each wave a 32x32 quarter of 2x2
 // v_mfma_f32_16x16x16_bf16 tiles; K staged through LDS 32 at a time.
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, Opnd A, Opnd B,
-                                                        float* __restrict__ C, long long ldc,
+// blockIdx.z takes the k range [z*kchunk, (z+1)*kchunk) and writes its
+// partial product at C + z*zstride (split K).
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, int kchunk, Opnd A,
+                                                        Opnd B, float* __restrict__ C,
+                                                        long long ldc, long long zstride,
                                                         const float* __restrict__ bias,
                                                         int accumulate) {
   __shared__ uint16_t As[64][36];
@@ -127,16 +152,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, Opn
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  C += blockIdx.z * zstride;
   f32x4 acc[2][2];
   for (int a = 0; a < 2; a++)
     for (int b = 0; b < 2; b++) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int r = e >> 5, kk = e & 31;
-      const int gi = i0 + r, gj = j0 + r, gk = k0 + kk;
-      As[r][kk] = (gi < M && gk < K) ? opnd_at(A, gi, gk) : (uint16_t)0;
-      Bs[r][kk] = (gj < N && gk < K) ? opnd_at(B, gj, gk) : (uint16_t)0;
-    }
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    stage_opnd(As, A, i0, M, k0, kend, tid);
+    stage_opnd(Bs, B, j0, N, k0, kend, tid);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 32; kk += 16) {
@@ -174,13 +197,47 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, Opn
       }
 }
 
+// out[i] = sum over z of part[z][i], z in increasing order (deterministic).
+__global__ void sum_splits_kernel(const float* __restrict__ part, int S, long long n,
+                                  float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < S; z++) s += part[z * n + i];
+  out[i] = s;
+}
+
+constexpr int kSplitMax = 32;  // partial products a split-K GEMM may keep
+
+// C = A B^T (+ bias, or += when accumulating).  With `part` (kSplitMax * M * N
+// floats) and a long K against few output tiles, K is split so that the
+// launch has about 512 workgroups, then the partials are summed in a fixed
+// order; split GEMMs write a dense C (ldc = N) without bias or accumulation.
 static maxss_status gemm(int M, int N, int K, const Opnd& A, const Opnd& B, float* C, long long ldc,
-                         const float* bias, bool accumulate, hipStream_t st) {
+                         const float* bias, bool accumulate, hipStream_t st,
+                         float* part = nullptr) {
   if (M <= 0 || N <= 0) return MAXSS_OK;
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int S = 1, kchunk = K;
+  if (part && !bias && !accumulate && ldc == N && K > 0) {
+    const int want = std::min(kSplitMax, std::max(1, (512 + tiles - 1) / tiles));
+    const int kblocks = (K + 31) / 32;
+    const int per = (kblocks + want - 1) / want;       // 32-wide k blocks per split
+    kchunk = per * 32;
+    S = (K + kchunk - 1) / kchunk;
+  }
   ProfScope prof("gemm", st);
-  gemm_bf16_kernel<<<grid, 256, 0, st>>>(M, N, K, A, B, C, ldc, bias, accumulate ? 1 : 0);
-  return check_hip(hipGetLastError(), "gemm_bf16_kernel");
+  if (S <= 1) {
+    dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
+    gemm_bf16_kernel<<<grid, 256, 0, st>>>(M, N, K, std::max(K, 1), A, B, C, ldc, 0, bias,
+                                           accumulate ? 1 : 0);
+    return check_hip(hipGetLastError(), "gemm_bf16_kernel");
+  }
+  const long long n = (long long)M * N;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, S);
+  gemm_bf16_kernel<<<grid, 256, 0, st>>>(M, N, K, kchunk, A, B, part, N, n, nullptr, 0);
+  sum_splits_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(part, S, n, C);
+  return check_hip(hipGetLastError(), "gemm_bf16_kernel (split K)");
 }
 
 // ------------------------------------------------------------ pair stage
@@ -588,7 +645,9 @@ static maxss_status ensure_train_scratch(Model* m, const Index* ix, uint32_t nb)
       (s = check_hip(hipMalloc((void**)&m->dH, 2ull * P * kH), "alloc")) ||
       (s = check_hip(hipMalloc((void**)&m->dA, 2ull * cap * kH), "alloc")) ||
       (s = check_hip(hipMalloc((void**)&m->part, 4ull * cap * (2 * kH + 1)), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->grad, 4ull * (kParams + 2 * kH * kD)), "alloc")) ||
+      (s = check_hip(hipMalloc((void**)&m->grad,
+                                4ull * (kParams + 2 * kH * kD + (size_t)kSplitMax * kH * kD)),
+                      "alloc")) ||
       (s = check_hip(hipMalloc((void**)&m->rsel, 4ull * cap), "alloc"))) {
     free_train_scratch(m);
     return s;
@@ -999,17 +1058,19 @@ extern "C" maxss_status maxss_model_train_step(maxss_model* model, const maxss_i
   train_bwd_kernel<<<nb, kH, 0, st>>>(m->Ar, m->Bc, m->w2f, m->dy, m->dH, m->dA, m->part);
   if ((s = check_hip(hipGetLastError(), "train fwd/bwd"))) return s;
   float* tmp = m->grad + kParams;  // [2][kH][kD] fp32 for dW1a, dW1b
+  float* split = tmp + 2 * kH * kD;  // split-K partials, [kSplitMax][kH][kD]
   {
     // dW1a[k][j] = sum_b dA[b][k] Vr[rsel[b]][j]
     Opnd a{m->dA, 1, kH, nullptr, nullptr};
     Opnd b{m->rprof, 1, kD, nullptr, m->rsel};
-    if ((s = gemm(kH, kD, (int)nb, a, b, tmp, kD, nullptr, false, st))) return s;
+    if ((s = gemm(kH, kD, (int)nb, a, b, tmp, kD, nullptr, false, st, split))) return s;
   }
   {
     // dW1b[k][j] = sum_p dH[p][k] Vf[cand[p]][j]
     Opnd a{m->dH, 1, kH, nullptr, nullptr};
     Opnd b{m->fprof, 1, kD, nullptr, cand};
-    if ((s = gemm(kH, kD, (int)P, a, b, tmp + kH * kD, kD, nullptr, false, st))) return s;
+    if ((s = gemm(kH, kD, (int)P, a, b, tmp + kH * kD, kD, nullptr, false, st, split)))
+      return s;
   }
   assemble_w1_kernel<<<(kW1 + 255) / 256, 256, 0, st>>>(tmp, m->grad);
   train_reduce_kernel<<<(2 * kH + 2 + 255) / 256, 256, 0, st>>>(m->part, m->lossv, nb, m->grad, loss);

@@ -189,6 +189,36 @@ def _train_batch(g, r, ix, seed, B=32):
     return sub, cand, strand
 
 
+def _grad_bound(sh, t, B):
+    """Per-parameter bound on |GPU gradient - oracle gradient|.
+
+    The GPU rounds the per-read pre-activation gradient dA[b,k] = sum_c dh
+    and the per-pair dh to bf16 (8 significant bits, round to nearest:
+    relative error at most 2^-8) before the weight-gradient
+    GEMMs, and accumulates in float32.  Upstream, y carries the forward
+    float32 error, which reaches p = softmax(y) and hence dy and dh with
+    relative error eps_up = 2 max|dy_err| + a few float32 units.  A ReLU
+    unit whose pre-activation lies within the forward error of zero may flip,
+    contributing |dy w2| to dh.
+    """
+    W1, b1, w2, b2 = mlp.unpack(sh)
+    z, pre, h, dy, dh = t["z"], t["pre"], t["h"], t["dy"], t["dh"]
+    n = z.shape[0]
+    pre_err = gamma(257) * (np.abs(z) @ np.abs(W1).T + np.abs(b1))
+    y_err = np.abs(w2) @ pre_err.T + gamma(257) * (np.abs(h) @ np.abs(w2) + abs(b2))
+    eps_up = 2 * y_err.max() + 8 * U
+    dh_abs = (np.abs(dh) + (np.abs(pre) <= pre_err) * np.abs(np.outer(dy, w2))) * (1 + eps_up)
+    ub = 2.0 ** -8
+    dA_abs = dh_abs.reshape(B, -1, 256).sum(axis=1)
+    vr = np.abs(z.reshape(B, -1, 512)[:, 0, :256])
+    bw1a = (ub + gamma(64) + gamma(B) + eps_up) * (dA_abs.T @ vr)
+    bw1b = (ub + gamma(n) + eps_up) * (dh_abs.T @ np.abs(z[:, 256:]))
+    bdb1 = (gamma(n) + eps_up) * dh_abs.sum(axis=0)
+    bdw2 = (gamma(n) + eps_up + gamma(257)) * (np.abs(h).T @ np.abs(dy)) + np.abs(dy) @ (pre_err * (np.abs(pre) <= pre_err))
+    bdb2 = (gamma(n) + eps_up) * np.abs(dy).sum()
+    return np.concatenate([np.concatenate([bw1a, bw1b], axis=1).ravel(), bdb1, bdw2, [bdb2]]) + 1e-12
+
+
 def test_train_step_gradient_matches_oracle(small):
     torch = _torch()
     g, r, ix = small
@@ -203,16 +233,13 @@ def test_train_step_gradient_matches_oracle(small):
     torch.cuda.synchronize()
     vf = mlp.bf16(mlp.fragment_profiles(g.seq.tobytes(), 2048))
     vr = np.stack([mlp.bf16(mlp.read_profiles(sub.read(b)))[strand[b]] for b in range(sub.n)])
-    ref_loss, _, ref_g = mlp.loss_and_grad(mlp.shadow(params), vr, vf[cand])
+    sh = mlp.shadow(params)
+    ref_loss, _, ref_g, t = mlp.loss_and_grad(sh, vr, vf[cand], parts=True)
     got_g = grad.cpu().numpy().astype(np.float64)
     assert abs(loss.item() - ref_loss) <= 1e-4 * max(1.0, ref_loss)
-    # bf16 dH / dA in the weight-gradient GEMMs: relative error ~2^-9 per term
-    rel = np.linalg.norm(got_g - ref_g) / np.linalg.norm(ref_g)
-    assert rel < 1e-2, rel
-    for lo, hi in [(0, 256 * 512), (256 * 512, 256 * 513), (256 * 513, 256 * 514)]:
-        part = np.linalg.norm(got_g[lo:hi] - ref_g[lo:hi]) / max(1e-12, np.linalg.norm(ref_g[lo:hi]))
-        assert part < 2e-2, (lo, part)
-    assert abs(got_g[-1] - ref_g[-1]) <= 1e-5
+    bound = _grad_bound(sh, t, sub.n)
+    err = np.abs(got_g - ref_g)
+    assert (err <= 2 * bound).all(), (np.argmax(err / (2 * bound)), (err / (2 * bound)).max())
     # lr = 0: parameters unchanged
     assert (m.params() == params).all()
     m.close()
