@@ -322,6 +322,25 @@ def sample_reads(genome: Genome, n: int, seed: int, lengths, rate_lo: float, rat
     return Reads(seq, off, start, span, strand, rate, n_ind)
 
 
+def sample_qualities(reads: Reads, seed: int, q_hi: int = 40, q_lo: int = 2) -> np.ndarray:
+    """Phred base qualities for `reads` as Phred+33 ASCII (uint8, the same CSR
+    layout as reads.seq).  Per base: 38 - 14 (d/m)^2 + 4 z rounded and clipped
+    to [q_lo, q_hi], where d is the distance from the read's first base, m
+    its length and z ~ N(0, 1) (Box-Muller on the seeded stream), so the
+    quality falls along the read with noise."""
+    st = Stream(seed, "reads.qual")
+    lens = np.diff(reads.offsets.astype(np.int64))
+    nb = int(lens.sum())
+    u1 = np.maximum(st.uniform(nb), 1e-300)
+    u2 = st.uniform(nb)
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    rid = np.repeat(np.arange(lens.size), lens)
+    d = np.arange(nb, dtype=np.int64) - reads.offsets[:-1].astype(np.int64)[rid]
+    m = np.maximum(lens[rid], 1).astype(np.float64)
+    q = np.rint(38.0 - 14.0 * (d / m) ** 2 + 4.0 * z)
+    return (np.clip(q, q_lo, q_hi).astype(np.int64) + 33).astype(np.uint8)
+
+
 # ---------------------------------------------------------------- workloads
 
 @dataclass

@@ -37,6 +37,7 @@
  *     default (whole read, free ends in the region), global mode on a flag;
  *     traceback priority on ties: diagonal, then up (I), then left (D).
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -131,16 +132,43 @@ int32_t oracle_maxss_seq(const int32_t* x, uint32_t n) {
   return B;
 }
 
+/* Position-specific scores from base qualities (Methods, paragraph on base
+ * qualities and the position specific scoring matrix).  With x = 1 -
+ * 10^(-Q/10) the probability that read base k is right (Q = qual[k] - 33,
+ * Phred+33), a match scores M x and a mismatch X x / 3 (the formula as
+ * printed), in integer units of 1/scale: sm[k] = lround(M * x * scale) and
+ * sx[k] = lround(X * x * scale / 3), evaluated left to right in double. */
+static int qual_scores(const char* qual, uint32_t m, int32_t M, int32_t X, int32_t scale,
+                       int32_t* sm, int32_t* sx) {
+  for (uint32_t k = 0; k < m; k++) {
+    const int c = (unsigned char)qual[k];
+    if (c < 33 || c > 126) return OR_EINVAL;
+    const double x = 1.0 - pow(10.0, -(double)(c - 33) / 10.0);
+    sm[k] = (int32_t)lround((double)M * x * (double)scale);
+    sx[k] = (int32_t)lround((double)X * x * (double)scale / 3.0);
+  }
+  return OR_OK;
+}
+
+/* Substitution score of read base k (q) against genome base g: M / X, or the
+ * read's position-specific pair when sm is given. */
+static inline int32_t pos_subst(char q, char g, uint32_t k, int32_t M, int32_t X,
+                                const int32_t* sm, const int32_t* sx) {
+  if (!sm) return subst(q, g, M, X);
+  return (q == g && q != 'N') ? sm[k] : sx[k];
+}
+
 /* MaxSS score of read q (length m, upper-case) against the genome window
  * starting at absolute position p: the maximum scoring subsequence of the
  * ungapped substitution scores subst(q[k], g[p+k]), k = 0..m-1.  With
  * step 2 (MaxSSmap_fast, Methods paragraph of that name) only the read
  * positions k = 0, 2, 4, ... enter the sequence, each against g[p+k]. */
 static int32_t window_score(const char* q, uint32_t m, const char* g, uint64_t G,
-                            uint64_t p, int32_t M, int32_t X, uint32_t step) {
+                            uint64_t p, int32_t M, int32_t X, uint32_t step,
+                            const int32_t* sm, const int32_t* sx) {
   int32_t H = 0, B = 0;
   for (uint32_t k = 0; k < m; k += step) {
-    H = H + subst(q[k], genome_at(g, G, p + k), M, X);
+    H = H + pos_subst(q[k], genome_at(g, G, p + k), k, M, X, sm, sx);
     if (H < 0) H = 0;
     if (H > B) B = H;
   }
@@ -148,14 +176,18 @@ static int32_t window_score(const char* q, uint32_t m, const char* g, uint64_t G
 }
 
 int oracle_window_score(const char* read, uint32_t m, const char* genome, uint64_t G,
-                        uint64_t p, int32_t M, int32_t X, uint32_t step, int32_t* out) {
+                        uint64_t p, int32_t M, int32_t X, uint32_t step, const char* qual,
+                        int32_t qscale, int32_t* out) {
   if (step != 1 && step != 2) return OR_EINVAL;
   char* q = normalise(read, m);
   char* g = normalise(genome, G);
-  if (!q || !g) { free(q); free(g); return OR_EINVAL; }
-  *out = window_score(q, m, g, G, p, M, X, step);
-  free(q); free(g);
-  return OR_OK;
+  int32_t* sm = qual ? (int32_t*)malloc(sizeof(int32_t) * (m ? m : 1)) : NULL;
+  int32_t* sx = qual ? (int32_t*)malloc(sizeof(int32_t) * (m ? m : 1)) : NULL;
+  int st = (!q || !g || (qual && (!sm || !sx))) ? OR_EINVAL : OR_OK;
+  if (st == OR_OK && qual) st = qual_scores(qual, m, M, X, qscale, sm, sx);
+  if (st == OR_OK) *out = window_score(q, m, g, G, p, M, X, step, sm, sx);
+  free(q); free(g); free(sm); free(sx);
+  return st;
 }
 
 /* --------------------------------------------------------- scan + top-2 */
@@ -165,6 +197,7 @@ int oracle_window_score(const char* read, uint32_t m, const char* genome, uint64
 static void fragment_values(const char* q_fwd, const char* q_rc, uint32_t m,
                             const char* g, uint64_t G, uint32_t F, uint32_t NF,
                             int32_t M, int32_t X, int one_strand, uint32_t step,
+                            const int32_t* const* sm, const int32_t* const* sx,
                             int32_t* v, int32_t* s_out, int32_t* o_out) {
   for (uint32_t f = 0; f < NF; f++) {
     int32_t best = -1, bs = 0, bo = 0;
@@ -172,7 +205,7 @@ static void fragment_values(const char* q_fwd, const char* q_rc, uint32_t m,
       const char* q = s == 0 ? q_fwd : q_rc;
       for (uint32_t o = 0; o < F; o++) {
         uint64_t p = (uint64_t)f * F + o;
-        int32_t sc = window_score(q, m, g, G, p, M, X, step);
+        int32_t sc = window_score(q, m, g, G, p, M, X, step, sm[s], sx[s]);
         if (sc > best) { best = sc; bs = s; bo = (int32_t)o; } /* strict: keeps smallest s, o */
       }
     }
@@ -204,6 +237,7 @@ typedef struct {
   const char* g; uint64_t G; uint32_t F, NF;
   const char* reads; const uint64_t* offsets; uint32_t n;
   int32_t M, X; int one_strand; uint32_t step;
+  const char* quals; int32_t qscale; /* optional Phred+33 qualities (CSR as reads) */
   int tid, nthreads;
   oracle_top2* out;
   int32_t* all_v; /* optional n x NF matrix of fragment values */
@@ -222,8 +256,29 @@ static void* scan_worker(void* arg) {
     char* rc = (char*)malloc(m ? m : 1);
     if (!q || !rc) { free(q); free(rc); J->status = OR_EINVAL; break; }
     oracle_revcomp(q, m, rc);
-    fragment_values(q, rc, m, J->g, J->G, J->F, J->NF, J->M, J->X, J->one_strand, J->step, v,
-                    s, o);
+    /* position-specific scores of each strand (reverse strand: reversed) */
+    int32_t* sm[2] = {NULL, NULL};
+    int32_t* sx[2] = {NULL, NULL};
+    if (J->quals) {
+      for (int t = 0; t < 2; t++) {
+        sm[t] = (int32_t*)malloc(sizeof(int32_t) * m);
+        sx[t] = (int32_t*)malloc(sizeof(int32_t) * m);
+      }
+      int bad = !sm[0] || !sm[1] || !sx[0] || !sx[1] ||
+                qual_scores(J->quals + J->offsets[i], m, J->M, J->X, J->qscale, sm[0], sx[0]);
+      if (!bad)
+        for (uint32_t k = 0; k < m; k++) {
+          sm[1][k] = sm[0][m - 1 - k];
+          sx[1][k] = sx[0][m - 1 - k];
+        }
+      if (bad) {
+        for (int t = 0; t < 2; t++) { free(sm[t]); free(sx[t]); }
+        free(q); free(rc); J->status = OR_EINVAL; break;
+      }
+    }
+    fragment_values(q, rc, m, J->g, J->G, J->F, J->NF, J->M, J->X, J->one_strand, J->step,
+                    (const int32_t* const*)sm, (const int32_t* const*)sx, v, s, o);
+    for (int t = 0; t < 2; t++) { free(sm[t]); free(sx[t]); }
     top_two(v, s, o, J->NF, &J->out[i]);
     if (J->all_v) memcpy(J->all_v + (uint64_t)i * J->NF, v, sizeof(int32_t) * J->NF);
     free(q); free(rc);
@@ -234,10 +289,13 @@ static void* scan_worker(void* arg) {
 
 /* Full scan: top-2 record per read.  reads is a CSR concatenation (offsets has
  * n+1 entries).  all_v (may be NULL) receives the n x NF fragment values.
- * flags: OR_ONE_STRAND, OR_FAST (every other read base, per strand). */
+ * flags: OR_ONE_STRAND, OR_FAST (every other read base, per strand).  quals
+ * (may be NULL): Phred+33 qualities laid out as the reads, scored with the
+ * position-specific pairs of qual_scores at scale qscale. */
 int oracle_scan(const char* genome, uint64_t G, uint32_t F, const char* reads,
                 const uint64_t* offsets, uint32_t n, int32_t M, int32_t X, uint32_t flags,
-                int nthreads, oracle_top2* out, int32_t* all_v) {
+                int nthreads, oracle_top2* out, int32_t* all_v, const char* quals,
+                int32_t qscale) {
   if (G == 0 || F == 0) return OR_EINVAL;
   for (uint32_t i = 0; i < n; i++)
     if (offsets[i + 1] <= offsets[i]) return OR_EINVAL;
@@ -250,7 +308,7 @@ int oracle_scan(const char* genome, uint64_t G, uint32_t F, const char* reads,
   if (!jobs || !th) { free(g); free(jobs); free(th); return OR_ENOMEM; }
   for (int t = 0; t < nthreads; t++) {
     scan_job J = {g, G, F, NF, reads, offsets, n, M, X, (flags & OR_ONE_STRAND) != 0,
-                  (flags & OR_FAST) ? 2u : 1u, t, nthreads, out, all_v, OR_OK};
+                  (flags & OR_FAST) ? 2u : 1u, quals, qscale, t, nthreads, out, all_v, OR_OK};
     jobs[t] = J;
     pthread_create(&th[t], NULL, scan_worker, &jobs[t]);
   }
@@ -275,20 +333,33 @@ int oracle_scan(const char* genome, uint64_t G, uint32_t F, const char* reads,
  * ('=' match, 'X' mismatch, 'I' read base against a gap, 'D' reference base
  * against a gap) in alignment order, NUL-terminated. */
 int oracle_nw(const char* read, uint32_t m, const char* ref, uint32_t n, int32_t M,
-              int32_t X, int32_t gap, int mode, int32_t* score, int32_t* jb, int32_t* je,
-              char* ops, uint32_t ops_cap, uint32_t* ops_len) {
+              int32_t X, int32_t gap, int mode, const char* qual, int32_t qscale,
+              int32_t* score, int32_t* jb, int32_t* je, char* ops, uint32_t ops_cap,
+              uint32_t* ops_len) {
   char* q = normalise(read, m);
   char* r = normalise(ref, n);
   if (!q || !r) { free(q); free(r); return OR_EINVAL; }
+  /* with qualities (in the read's orientation as given): row i scores with
+   * the pair of read base i, and the gap is in the same 1/scale units */
+  int32_t* sm = NULL;
+  int32_t* sx = NULL;
+  if (qual) {
+    sm = (int32_t*)malloc(sizeof(int32_t) * (m ? m : 1));
+    sx = (int32_t*)malloc(sizeof(int32_t) * (m ? m : 1));
+    if (!sm || !sx || qual_scores(qual, m, M, X, qscale, sm, sx)) {
+      free(sm); free(sx); free(q); free(r); return OR_EINVAL;
+    }
+    gap = gap * qscale;
+  }
   uint64_t W = (uint64_t)n + 1;
   int32_t* D = (int32_t*)malloc(sizeof(int32_t) * (uint64_t)(m + 1) * W);
-  if (!D) { free(q); free(r); return OR_ENOMEM; }
+  if (!D) { free(sm); free(sx); free(q); free(r); return OR_ENOMEM; }
 #define DP(i, j) D[(uint64_t)(i) * W + (j)]
   for (uint32_t j = 0; j <= n; j++) DP(0, j) = (mode == OR_NW_GLOBAL) ? (int32_t)j * gap : 0;
   for (uint32_t i = 1; i <= m; i++) {
     DP(i, 0) = (int32_t)i * gap;
     for (uint32_t j = 1; j <= n; j++) {
-      int32_t d = DP(i - 1, j - 1) + subst(q[i - 1], r[j - 1], M, X);
+      int32_t d = DP(i - 1, j - 1) + pos_subst(q[i - 1], r[j - 1], i - 1, M, X, sm, sx);
       int32_t u = DP(i - 1, j) + gap;
       int32_t l = DP(i, j - 1) + gap;
       int32_t b = d;
@@ -310,11 +381,12 @@ int oracle_nw(const char* read, uint32_t m, const char* ref, uint32_t n, int32_t
   /* traceback, collected backwards */
   uint64_t cap = (uint64_t)m + n + 1;
   char* rev = (char*)malloc(cap);
-  if (!rev) { free(D); free(q); free(r); return OR_ENOMEM; }
+  if (!rev) { free(D); free(sm); free(sx); free(q); free(r); return OR_ENOMEM; }
   uint64_t len = 0;
   uint32_t i = m, j = jend;
   while (i > 0 || (mode == OR_NW_GLOBAL && j > 0)) {
-    if (i > 0 && j > 0 && DP(i, j) == DP(i - 1, j - 1) + subst(q[i - 1], r[j - 1], M, X)) {
+    if (i > 0 && j > 0 &&
+        DP(i, j) == DP(i - 1, j - 1) + pos_subst(q[i - 1], r[j - 1], i - 1, M, X, sm, sx)) {
       rev[len++] = (q[i - 1] == r[j - 1] && q[i - 1] != 'N') ? '=' : 'X';
       i--; j--;
     } else if (i > 0 && DP(i, j) == DP(i - 1, j) + gap) {
@@ -335,7 +407,7 @@ int oracle_nw(const char* read, uint32_t m, const char* ref, uint32_t n, int32_t
   }
   *ops_len = (uint32_t)len;
 #undef DP
-  free(rev); free(D); free(q); free(r);
+  free(rev); free(D); free(sm); free(sx); free(q); free(r);
   return st;
 }
 
@@ -380,27 +452,31 @@ typedef struct {
  * each side and clipped to the genome.  CIGAR (run-length) goes to cigar. */
 int oracle_align_one(const char* genome, uint64_t G, uint32_t F, const char* read,
                      uint32_t m, int32_t frag, int32_t strand, uint32_t pad, int32_t M,
-                     int32_t X, int32_t gap, int mode, oracle_aln* out, char* cigar,
-                     uint32_t cigar_cap) {
+                     int32_t X, int32_t gap, int mode, const char* qual, int32_t qscale,
+                     oracle_aln* out, char* cigar, uint32_t cigar_cap) {
   if (frag < 0 || m == 0) return OR_EINVAL;
   char* q = normalise(read, m);
   if (!q) return OR_EINVAL;
   char* qq = (char*)malloc(m);
-  if (!qq) { free(q); return OR_ENOMEM; }
+  char* ql = qual ? (char*)malloc(m) : NULL;
+  if (!qq || (qual && !ql)) { free(q); free(qq); free(ql); return OR_ENOMEM; }
   if (strand) oracle_revcomp(q, m, qq); else memcpy(qq, q, m);
+  if (qual)  /* qualities follow the read: reversed on the reverse strand */
+    for (uint32_t k = 0; k < m; k++) ql[k] = strand ? qual[m - 1 - k] : qual[k];
   int64_t start = (int64_t)frag * F;
   int64_t a = start - (int64_t)pad;
   if (a < 0) a = 0;
   int64_t b = start + (int64_t)F + (int64_t)m - 1 + (int64_t)pad;
   if (b > (int64_t)G) b = (int64_t)G;
-  if (b <= a) { free(q); free(qq); return OR_EINVAL; }
+  if (b <= a) { free(q); free(qq); free(ql); return OR_EINVAL; }
   uint32_t n = (uint32_t)(b - a);
   uint32_t cap = m + n + 1;
   char* ops = (char*)malloc(cap);
-  if (!ops) { free(q); free(qq); return OR_ENOMEM; }
+  if (!ops) { free(q); free(qq); free(ql); return OR_ENOMEM; }
   int32_t sc, jb, je;
   uint32_t olen;
-  int st = oracle_nw(qq, m, genome + a, n, M, X, gap, mode, &sc, &jb, &je, ops, cap, &olen);
+  int st = oracle_nw(qq, m, genome + a, n, M, X, gap, mode, ql, qscale, &sc, &jb, &je, ops, cap,
+                     &olen);
   if (st == OR_OK) {
     memset(out, 0, sizeof(*out));
     out->score = sc;
@@ -410,6 +486,6 @@ int oracle_align_one(const char* genome, uint64_t G, uint32_t F, const char* rea
     st = oracle_cigar_rle(ops, cigar, cigar_cap);
     out->cigar_len = st == OR_OK ? (uint32_t)strlen(cigar) : 0;
   }
-  free(ops); free(q); free(qq);
+  free(ops); free(q); free(qq); free(ql);
   return st;
 }
