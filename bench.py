@@ -75,18 +75,31 @@ def cpu_baseline(w, budget_s: float = 15.0):
     oracle.align_top(w.genome.seq, w.F, sub.seq, sub.offsets, top, w.pad, w.M, w.X, w.gap)
     dt = time.perf_counter() - t0
     cells = 2.0 * G * float(sub.lengths().sum())
+    # one thread, on a quarter of one thread's share of the sample (about a
+    # quarter of the multi-threaded run's time)
+    k1 = max(1, int(0.25 * k / threads))
+    one = w.reads.subset(np.arange(k1))
+    t0 = time.perf_counter()
+    top = oracle.scan(w.genome.seq, w.F, one.seq, one.offsets, w.M, w.X, nthreads=1)
+    oracle.align_top(w.genome.seq, w.F, one.seq, one.offsets, top, w.pad, w.M, w.X, w.gap)
+    dt1 = time.perf_counter() - t0
+    cells1 = 2.0 * G * float(one.lengths().sum())
     return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads,
             "kind": "oracle",
             "sample": "%d of the %d reads (scan both strands + top-2 + NW), %.1f s" % (
-                k, w.reads.n, dt)}
+                k, w.reads.n, dt),
+            "single_thread": {"value": round(cells1 / dt1 / 1e9, 3), "cores": 1,
+                              "sample": "%d reads, %.1f s" % (k1, dt1)}}
 
 
 def proposal_leg(ix, w, seq, off, top_full, stream, args):
-    """Learned proposal on the bacterial genome: train on plain-scan labels of
-    `train_reads` reads (own seed), choose the margin threshold on a 10%
-    held-out split for >= 99.5% top-1 agreement there, then time the
-    proposal path and the full scan on the workload's reads (already in HBM)
-    and report reads/s and top-1 agreement with the full scan."""
+    """Learned proposal on the workload's genome: train on plain-scan labels
+    of reads drawn like the workload's with their own seed (bacterial:
+    `train_reads`; damaged: `damaged_train_reads`), choose the margin
+    threshold on a 10% held-out split for >= 99.5% top-1 agreement there,
+    then time the proposal path and the full scan on the workload's reads
+    (already in HBM) and report reads/s and top-1 agreement with the full
+    scan."""
     import numpy as np
     import torch
 
@@ -94,7 +107,10 @@ def proposal_leg(ix, w, seq, off, top_full, stream, args):
     import paper_1403_2136_amd as mx
     from paper_1403_2136_amd import proposal as P
     t0 = time.time()
-    tw = gen.workload("proposal_train", n_reads=args.train_reads)
+    if w.name == "bacterial":
+        tw = gen.workload("proposal_train", n_reads=args.train_reads)
+    else:
+        tw = gen.workload(w.name, n_reads=args.damaged_train_reads, read_seed=53)
     nval = tw.reads.n // 10
     val = tw.reads.subset(np.arange(nval))
     trn = tw.reads.subset(np.arange(nval, tw.reads.n))
@@ -122,16 +138,21 @@ def proposal_leg(ix, w, seq, off, top_full, stream, args):
     fbt = torch.empty(n, dtype=torch.uint8, device="cuda")
     model.scan(ix, seq, off, args.K, tau, out, fbt, stream=stream)   # warm-up
     torch.cuda.synchronize()
-    reps = 3
-    t2 = time.perf_counter()
-    for _ in range(reps):
+    log("proposal: warm-up pass done")
+    reps = 3 if w.name == "bacterial" else 1     # a damaged-workload pass takes about a minute
+    t_prop = 0.0
+    for rep in range(reps):
+        t2 = time.perf_counter()
         model.scan(ix, seq, off, args.K, tau, out, fbt, stream=stream)
-    torch.cuda.synchronize()
-    t_prop = (time.perf_counter() - t2) / reps
+        torch.cuda.synchronize()
+        t_prop += time.perf_counter() - t2
+        log("proposal: timed pass %d done" % rep)
+    t_prop /= reps
     t3 = time.perf_counter()
     ix.scan(seq, off, top_full, stream=stream)
     torch.cuda.synchronize()
     t_full = time.perf_counter() - t3
+    log("proposal: full scan timed")
     got = out.cpu().numpy().view(mx.TOP2_DTYPE)
     ref = top_full.cpu().numpy().view(mx.TOP2_DTYPE)
     res = {"reads_per_s": round(n / t_prop, 1), "full_scan_reads_per_s": round(n / t_full, 1),
@@ -148,6 +169,68 @@ def proposal_leg(ix, w, seq, off, top_full, stream, args):
     return res
 
 
+def fast_leg(w, seq, off, top_full, full_scan_ms, stream):
+    """MaxSSmap_fast (every other read base scored): scan time against the
+    full scan's on the same reads, and top-1 agreement with the full scan."""
+    import numpy as np
+    import torch
+
+    import paper_1403_2136_amd as mx
+    from paper_1403_2136_amd import proposal as P
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap, flags=mx.MAXSS_FAST)
+    n = w.reads.n
+    out = torch.empty(n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(seq, off, out, stream=stream)
+    torch.cuda.synchronize()
+    mx.maxss_profile_enable(True)
+    ix.scan(seq, off, out, stream=stream)
+    torch.cuda.synchronize()
+    ms, k = mx.maxss_profile_read("scan")
+    mx.maxss_profile_enable(False)
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    ref = top_full.cpu().numpy().view(mx.TOP2_DTYPE)
+    half = (w.reads.lengths().astype(np.int64) + 1) // 2
+    cells = 2.0 * w.genome.G * float(half.sum())
+    ix.close()
+    res = {"scan_ms_per_launch": round(ms / max(k, 1), 3),
+           "full_scan_ms_per_launch": round(full_scan_ms, 3),
+           "speedup": round(full_scan_ms / (ms / max(k, 1)), 3),
+           "fast_gcups_kernel": round(cells / (ms / max(k, 1) / 1e3) / 1e9, 1),
+           "top1_agreement": round(P.top1_agreement(got, ref), 5)}
+    log("fast: %s" % res)
+    return res
+
+
+def qual_leg(w, seq, off, full_scan_ms, stream, scale: int = 10):
+    """Base-quality scoring (position-specific scores from synthetic Phred
+    qualities at 1/scale resolution): scan time against the plain scan's on
+    the same reads."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1403_2136_amd as mx
+    q = torch.from_numpy(gen.sample_qualities(w.reads, 91)).cuda()
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap, qual_scale=scale)
+    n = w.reads.n
+    out = torch.empty(n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(seq, off, out, stream=stream, qual=q)
+    torch.cuda.synchronize()
+    mx.maxss_profile_enable(True)
+    ix.scan(seq, off, out, stream=stream, qual=q)
+    torch.cuda.synchronize()
+    ms, k = mx.maxss_profile_read("scan")
+    mx.maxss_profile_enable(False)
+    ix.close()
+    cells = 2.0 * w.genome.G * float(w.reads.lengths().astype(np.int64).sum())
+    res = {"qual_scale": scale, "scan_ms_per_launch": round(ms / max(k, 1), 3),
+           "plain_scan_ms_per_launch": round(full_scan_ms, 3),
+           "gcups_kernel": round(cells / (ms / max(k, 1) / 1e3) / 1e9, 1),
+           "slowdown": round((ms / max(k, 1)) / full_scan_ms, 3)}
+    log("qual: %s" % res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,7 +243,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-proposal", action="store_true",
                     help="skip the learned-proposal leg (training + reads/s vs the full scan)")
+    ap.add_argument("--no-qual", action="store_true",
+                    help="skip the base-quality scoring leg")
+    ap.add_argument("--no-fast", action="store_true",
+                    help="skip the MaxSSmap_fast leg (every other read base scored)")
     ap.add_argument("--train-reads", type=int, default=200_000)
+    ap.add_argument("--damaged-train-reads", type=int, default=22_000,
+                    help="training + validation reads of the damaged workload's proposal leg "
+                         "(labels cost a full scan of the 248 Mbp genome each)")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -211,7 +301,7 @@ def main():
     if batched:
         # one persistent scan launch per mixed-length batch, replayed from a
         # captured HIP graph; tiles from the autotuner (parity-gated)
-        sample = w.reads.subset(np.arange(0, n, max(1, n // 2000))[:2000])
+        sample = w.reads.subset(np.arange(0, n, max(1, n // 512))[:512])
         tune = ix.autotune(sample.seq, sample.offsets)
         log("autotune: %s" % tune)
         plan = mx.Plan(ix, capacity=n, pad=w.pad, cigar_stride=stride)
@@ -296,7 +386,19 @@ def main():
     }
     if tune is not None:
         res["config"]["autotune"] = tune
-    if not args.no_proposal and w.name == "bacterial":
+    if not batched:
+        # PCIe-inclusive: one scan of host buffers (reads copied in, records
+        # copied out inside the call); reported beside, never as, the value
+        t0 = time.perf_counter()
+        ix.scan(w.reads.seq, w.reads.offsets)
+        t_e2e = time.perf_counter() - t0
+        res["config"]["scan_host_buffers_s"] = round(t_e2e, 3)
+        res["config"]["scan_host_buffers_gcups"] = round(cells / t_e2e / 1e9, 1)
+    if not args.no_fast and not batched:
+        res["fast"] = fast_leg(w, seq, off, top, scan_s * 1e3, stream)
+    if not args.no_qual and not batched:
+        res["qual"] = qual_leg(w, seq, off, scan_s * 1e3, stream)
+    if not args.no_proposal and w.name in ("bacterial", "damaged"):
         res["proposal"] = proposal_leg(ix, w, seq, off, top, stream, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

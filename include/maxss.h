@@ -49,6 +49,10 @@ typedef enum {
 /* maxss_params.flags */
 #define MAXSS_ONE_STRAND 1u /* scan only the read as given (no reverse complement) */
 #define MAXSS_NW_GLOBAL 2u  /* end-to-end NW instead of fitting the whole read     */
+#define MAXSS_FAST 4u       /* MaxSSmap_fast (Methods paragraph of that name): the
+                             * first phase scores read positions 0, 2, 4, ... of
+                             * each strand only, each against the genome base
+                             * at the same distance from the window start      */
 
 /* Scoring and fragmenting parameters, fixed when the genome is indexed.
  *   match        M, score of two equal bases (not N); 1..127.
@@ -58,7 +62,18 @@ typedef enum {
  *                "Byte packing for faster global memory access").
  *   max_read_len longest read any later call may pass; 1..8192 and
  *                max_read_len * match <= 65535 (the scan's 16-bit exact range).
- *   flags        MAXSS_ONE_STRAND, MAXSS_NW_GLOBAL. */
+ *   flags        MAXSS_ONE_STRAND, MAXSS_NW_GLOBAL, MAXSS_FAST.
+ *   qual_scale   0: plain match / mismatch scores.  > 0: reads carry base
+ *                qualities and both phases score with a position-specific
+ *                matrix (Methods, paragraph on base qualities and the
+ *                position specific scoring matrix): with x = 1 - 10^(-Q/10)
+ *                (Q = Phred+33 quality - 33) a match scores M x and a
+ *                mismatch X x / 3, in integer units of 1/qual_scale rounded
+ *                half away from zero (lround of M*x*s and X*x*s/3 in double,
+ *                left to right); N scores the mismatch of its position; the
+ *                gap of the second phase is gap*qual_scale.  Requires
+ *                match*qual_scale <= 127, -mismatch*qual_scale <= 381 and
+ *                max_read_len*match*qual_scale <= 65535. */
 typedef struct {
   int32_t match;
   int32_t mismatch;
@@ -66,6 +81,7 @@ typedef struct {
   uint32_t frag_len;
   uint32_t max_read_len;
   uint32_t flags;
+  uint32_t qual_scale;
 } maxss_params;
 
 typedef struct maxss_index maxss_index; /* opaque, immutable once built */
@@ -78,6 +94,10 @@ typedef struct {
   const uint64_t* offsets;
   uint32_t n;
   uint32_t on_device;
+  const char* qual;  /* Phred+33 qualities laid out as seq (same offsets, same
+                      * memory kind), or NULL; required when the index has
+                      * qual_scale > 0, ignored otherwise.  A quality outside
+                      * '!'..'~' makes the read invalid like a bad base. */
 } maxss_reads;
 
 /* Per-read result of the scan (32 bytes).  Entry 0 is the best fragment,
@@ -308,6 +328,48 @@ maxss_status maxss_model_train_step(maxss_model* model, const maxss_index* index
                                     const maxss_reads* batch, const int32_t* cand,
                                     const int8_t* strand, float lr, float* loss, float* grad,
                                     void* stream);
+
+/* ---------------------------------------------------------------- SAM output
+ * Mapping quality and SAM records (Methods, paragraph on mapping qualities,
+ * read lengths, SAM output and source code; the 0.9 ratio rule of the
+ * first-phase paragraph; the threshold 62 of the ancient-DNA Results). */
+
+/* Per read: mapq[i] = the integer part of -100 log2(score[1] / score[0]),
+ * capped at 254; 254 when there is no second fragment or its score is 0; 0
+ * when the best score is 0 or the read is invalid.  mapped[i] (may be NULL)
+ * = 1 when score[0] > 0, max(score[1], 0) * ratio_den < score[0] * ratio_num
+ * (exact integers; 9/10 is the paper's rule) and mapq[i] > min_mapq (-1
+ * disables; 62 is the strict setting).  Device pointers (top: n records,
+ * mapq and mapped: n bytes), asynchronous on `stream`.
+ * Errors: EINVAL (NULL, ratio_den = 0), EDEVICE. */
+maxss_status maxss_mapq(const maxss_top2* top, uint32_t n, uint32_t ratio_num,
+                        uint32_t ratio_den, int32_t min_mapq, uint8_t* mapq, uint8_t* mapped,
+                        void* stream);
+
+/* SAM header: @HD (VN:1.6, SO:unsorted), @SQ (SN:rname, LN:G), @PG.  Host
+ * buffer of `cap` bytes, not NUL-terminated; *len = bytes written, or needed
+ * when the call fails with EINVAL because cap is too small.
+ * Errors: EINVAL (NULL, rname empty or not printable without spaces, cap). */
+maxss_status maxss_sam_header(const maxss_index* index, const char* rname, char* buf,
+                              uint64_t cap, uint64_t* len);
+
+/* One SAM line per read, in read order, from host copies of the first and
+ * second phase's outputs: QNAME (names[i], or "r<i>" when names is NULL),
+ * FLAG (0, 16 for the reverse strand, 4 unmapped), RNAME, POS (ref_begin+1),
+ * MAPQ, CIGAR (the extended =/X/I/D string, "*" if truncated), RNEXT "*",
+ * PNEXT 0, TLEN 0, SEQ (the read on the forward genome strand: reverse
+ * complement for strand 1), QUAL "*", then AS:i:<NW score>.  An unmapped read
+ * has RNAME "*", POS 0, MAPQ 0, CIGAR "*" and SEQ as given (upper case); a
+ * read the scan marked invalid has SEQ "*".  All pointers are host pointers:
+ * reads (on_device = 0), top and aln (n records), cigar (n * cigar_stride
+ * bytes, NUL-terminated rows as written by maxss_align_top), mapq and mapped
+ * (n bytes, from maxss_mapq).  Output as for maxss_sam_header.
+ * Errors: EINVAL (NULL, device reads, bad names, cap), with *len = needed. */
+maxss_status maxss_sam_records(const maxss_reads* reads, const maxss_top2* top,
+                               const maxss_aln* aln, const char* cigar, uint64_t cigar_stride,
+                               const uint8_t* mapq, const uint8_t* mapped, const char* rname,
+                               const char* const* names, char* buf, uint64_t cap,
+                               uint64_t* len);
 
 /* Kernel timing for measurement.  maxss_profile_enable(1) clears the records
  * and brackets every later launch of the library's kernels with HIP events on

@@ -24,6 +24,7 @@ MAXSS_ETOOLONG = -4
 MAXSS_ESTATE = -5
 MAXSS_ONE_STRAND = 1
 MAXSS_NW_GLOBAL = 2
+MAXSS_FAST = 4
 MAXSS_READ_INVALID = -2
 MAXSS_ALN_TRUNCATED = 1
 MAXSS_ALN_SKIPPED = 2
@@ -46,7 +47,7 @@ class MaxssError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap", ctypes.c_int32),
                 ("frag_len", ctypes.c_uint32), ("max_read_len", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("qual_scale", ctypes.c_uint32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -58,7 +59,7 @@ class TuneResult(ctypes.Structure):
 
 class Reads(ctypes.Structure):
     _fields_ = [("seq", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_uint32),
-                ("on_device", ctypes.c_uint32)]
+                ("on_device", ctypes.c_uint32), ("qual", ctypes.c_void_p)]
 
 
 # every function declared in include/maxss.h
@@ -68,6 +69,7 @@ EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_
            "maxss_model_create", "maxss_model_free", "maxss_model_get_params", "maxss_model_save",
            "maxss_model_load", "maxss_profiles", "maxss_proposal_scores",
            "maxss_proposal_candidates", "maxss_scan_reads_proposed", "maxss_model_train_step",
+           "maxss_mapq", "maxss_sam_header", "maxss_sam_records",
            "maxss_profile_enable", "maxss_profile_read", "maxss_last_error", "maxss_version")
 MLP_PARAMS = 131585
 
@@ -150,6 +152,17 @@ def lib():
         L.maxss_last_error.argtypes = []
         L.maxss_version.restype = c.c_char_p
         L.maxss_version.argtypes = []
+        L.maxss_mapq.restype = c.c_int
+        L.maxss_mapq.argtypes = [c.c_void_p, c.c_uint32, c.c_uint32, c.c_uint32, c.c_int32,
+                                 c.c_void_p, c.c_void_p, c.c_void_p]
+        L.maxss_sam_header.restype = c.c_int
+        L.maxss_sam_header.argtypes = [c.c_void_p, c.c_char_p, c.c_void_p, c.c_uint64,
+                                       c.POINTER(c.c_uint64)]
+        L.maxss_sam_records.restype = c.c_int
+        L.maxss_sam_records.argtypes = [c.POINTER(Reads), c.c_void_p, c.c_void_p, c.c_void_p,
+                                        c.c_uint64, c.c_void_p, c.c_void_p, c.c_char_p,
+                                        c.c_void_p, c.c_void_p, c.c_uint64,
+                                        c.POINTER(c.c_uint64)]
         _lib = L
     return _lib
 
@@ -204,9 +217,10 @@ def maxss_profile_read(name: str):
 
 
 def maxss_index_genome(seq, frag_len: int, max_read_len: int, match: int = 1,
-                       mismatch: int = -1, gap: int = -2, flags: int = 0) -> int:
+                       mismatch: int = -1, gap: int = -2, flags: int = 0,
+                       qual_scale: int = 0) -> int:
     g = _as_u8(seq)
-    p = Params(match, mismatch, gap, frag_len, max_read_len, flags)
+    p = Params(match, mismatch, gap, frag_len, max_read_len, flags, qual_scale)
     h = ctypes.c_void_p()
     _check(lib().maxss_index_genome(g.ctypes.data, g.size, ctypes.byref(p), ctypes.byref(h)))
     return h.value
@@ -234,12 +248,24 @@ def _host_csr(seq, offsets):
     return s, off
 
 
-def _reads_struct(seq, offsets, on_device: bool) -> Reads:
+def _reads_struct(seq, offsets, on_device: bool, qual=None) -> Reads:
     n = (offsets.numel() if hasattr(offsets, "numel") else len(offsets)) - 1
-    return Reads(_ptr(seq), _ptr(offsets), n, 1 if on_device else 0)
+    if qual is not None and hasattr(qual, "numel") and hasattr(seq, "numel"):
+        assert qual.numel() >= seq.numel(), "one quality per read base"
+    return Reads(_ptr(seq), _ptr(offsets), n, 1 if on_device else 0, _ptr(qual))
 
 
-def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None):
+def _host_qual(qual, s: np.ndarray):
+    """Host qualities as a uint8 array of the reads' size, or None."""
+    if qual is None:
+        return None
+    q = _as_u8(qual)
+    if q.size != s.size:
+        raise ValueError("one quality per read base (%d qualities, %d bases)" % (q.size, s.size))
+    return q
+
+
+def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None, qual=None):
     """Top-2 records for a batch of reads.
 
     Host form: seq (bytes / uint8 array), offsets (uint64 array, n+1) ->
@@ -247,36 +273,38 @@ def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None):
     torch device tensors (uint8, int64 holding the offsets) and `out` a torch
     device tensor of n*32 bytes; the call is asynchronous on `stream`."""
     if hasattr(seq, "is_cuda") and seq.is_cuda:
-        r = _reads_struct(seq, offsets, True)
+        r = _reads_struct(seq, offsets, True, qual)
         if out is None:
             raise ValueError("device reads need a device `out` tensor of n*32 bytes")
         _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), _ptr(out),
                                       _stream_handle(stream)))
         return out
     s, off = _host_csr(seq, offsets)
+    q = _host_qual(qual, s)
     n = off.size - 1
     res = np.zeros(n, dtype=TOP2_DTYPE) if out is None else out
-    r = Reads(s.ctypes.data, off.ctypes.data, n, 0)
+    r = Reads(s.ctypes.data, off.ctypes.data, n, 0, _ptr(q))
     _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), res.ctypes.data,
                                   _stream_handle(stream)))
     return res
 
 
 def maxss_align_top(handle: int, seq, offsets, top, pad: int = 100, cigar_stride: int = 512,
-                    out=None, cigar=None, stream=None):
+                    out=None, cigar=None, stream=None, qual=None):
     """Second phase.  Host form returns (ALN_DTYPE array, list of CIGAR str);
     device form fills `out` (n*32 bytes) and `cigar` (n*cigar_stride bytes)."""
     if hasattr(seq, "is_cuda") and seq.is_cuda:
-        r = _reads_struct(seq, offsets, True)
+        r = _reads_struct(seq, offsets, True, qual)
         _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), _ptr(top), pad, _ptr(out),
                                      _ptr(cigar), cigar_stride, _stream_handle(stream)))
         return out, cigar
     s, off = _host_csr(seq, offsets)
+    q = _host_qual(qual, s)
     n = off.size - 1
     top = np.ascontiguousarray(top, dtype=TOP2_DTYPE)
     res = np.zeros(n, dtype=ALN_DTYPE)
     cig = np.zeros(n * cigar_stride, dtype=np.uint8)
-    r = Reads(s.ctypes.data, off.ctypes.data, n, 0)
+    r = Reads(s.ctypes.data, off.ctypes.data, n, 0, _ptr(q))
     _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), top.ctypes.data, pad,
                                  res.ctypes.data, cig.ctypes.data, cigar_stride,
                                  _stream_handle(stream)))
@@ -295,24 +323,25 @@ def maxss_plan_free(plan: int) -> None:
 
 
 def maxss_plan_run(plan: int, seq, offsets, top, aln=None, cigar=None, stream=None,
-                   graph: bool = False):
+                   graph: bool = False, qual=None):
     """One step on device reads (torch tensors); `graph` replays a captured
     HIP graph (needs a non-default stream)."""
-    r = _reads_struct(seq, offsets, True)
+    r = _reads_struct(seq, offsets, True, qual)
     fn = lib().maxss_plan_run_graph if graph else lib().maxss_plan_run
     _check(fn(plan, ctypes.byref(r), _ptr(top), _ptr(aln), _ptr(cigar), _stream_handle(stream)))
 
 
-def maxss_autotune(handle, seq, offsets, cache_path: str | None = None) -> dict:
+def maxss_autotune(handle, seq, offsets, cache_path: str | None = None, qual=None) -> dict:
     """Tune the index's tile shape on a sample (host arrays or device tensors)."""
     res = TuneResult()
     if hasattr(seq, "is_cuda") and seq.is_cuda:
-        r = _reads_struct(seq, offsets, True)
+        r = _reads_struct(seq, offsets, True, qual)
         keep = None
     else:
         s, off = _host_csr(seq, offsets)
-        r = Reads(s.ctypes.data, off.ctypes.data, off.size - 1, 0)
-        keep = (s, off)
+        q = _host_qual(qual, s)
+        r = Reads(s.ctypes.data, off.ctypes.data, off.size - 1, 0, _ptr(q))
+        keep = (s, off, q)
     _check(lib().maxss_autotune(h_(handle), ctypes.byref(r),
                                 cache_path.encode() if cache_path else None, ctypes.byref(res)))
     del keep
@@ -321,6 +350,56 @@ def maxss_autotune(handle, seq, offsets, cache_path: str | None = None) -> dict:
 
 def maxss_index_set_tiles(handle, np_: int = 0, reads_per_tile: int = 0, rounds: int = 0) -> None:
     _check(lib().maxss_index_set_tiles(h_(handle), np_, reads_per_tile, rounds))
+
+
+def maxss_mapq(top, n: int, mapq, mapped=None, ratio_num: int = 9, ratio_den: int = 10,
+               min_mapq: int = -1, stream=None) -> None:
+    """Mapping quality of n top-2 records (device tensors: top n*32 bytes,
+    mapq and mapped n bytes each)."""
+    _check(lib().maxss_mapq(_ptr(top), n, ratio_num, ratio_den, min_mapq, _ptr(mapq),
+                            _ptr(mapped), _stream_handle(stream)))
+
+
+def _two_pass(call) -> str:
+    """Run a formatting call once for its size, then into a buffer."""
+    need = ctypes.c_uint64()
+    st = call(None, 0, ctypes.byref(need))
+    if st == 0:
+        return ""
+    buf = ctypes.create_string_buffer(max(1, need.value))
+    _check(call(buf, need.value, ctypes.byref(need)))
+    return buf.raw[:need.value].decode()
+
+
+def maxss_sam_header(handle, rname: str) -> str:
+    r = rname.encode()
+    return _two_pass(lambda b, cap, ln: lib().maxss_sam_header(h_(handle), r, b, cap, ln))
+
+
+def maxss_sam_records(seq, offsets, top: np.ndarray, aln: np.ndarray, cigar: np.ndarray,
+                      cigar_stride: int, mapq: np.ndarray, mapped: np.ndarray, rname: str,
+                      names=None) -> str:
+    """SAM lines from host copies of the records (numpy arrays)."""
+    s, off = _host_csr(seq, offsets)
+    n = off.size - 1
+    r = Reads(s.ctypes.data, off.ctypes.data, n, 0)
+    top = np.ascontiguousarray(top)
+    aln = np.ascontiguousarray(aln)
+    cig = np.ascontiguousarray(cigar, dtype=np.uint8)
+    q = np.ascontiguousarray(mapq, dtype=np.uint8)
+    mp = np.ascontiguousarray(mapped, dtype=np.uint8)
+    assert top.size >= n and aln.size >= n and q.size >= n and mp.size >= n
+    assert cig.size >= n * cigar_stride
+    nm = None
+    if names is not None:
+        enc = [x.encode() for x in names]
+        assert len(enc) >= n
+        nm = (ctypes.c_char_p * len(enc))(*enc)
+    rn = rname.encode()
+    return _two_pass(lambda b, cap, ln: lib().maxss_sam_records(
+        ctypes.byref(r), top.ctypes.data, aln.ctypes.data, cig.ctypes.data, cigar_stride,
+        q.ctypes.data, mp.ctypes.data, rn, ctypes.cast(nm, ctypes.c_void_p) if nm else None,
+        b, cap, ln))
 
 
 def decode_cigar(buf: np.ndarray, i: int, stride: int) -> str:
@@ -344,8 +423,8 @@ class Plan:
         self.handle = maxss_plan_create(index.handle, capacity, pad, cigar_stride)
         self.capacity, self.pad, self.cigar_stride = capacity, pad, cigar_stride
 
-    def run(self, seq, offsets, top, aln=None, cigar=None, stream=None, graph=False):
-        maxss_plan_run(self.handle, seq, offsets, top, aln, cigar, stream, graph)
+    def run(self, seq, offsets, top, aln=None, cigar=None, stream=None, graph=False, qual=None):
+        maxss_plan_run(self.handle, seq, offsets, top, aln, cigar, stream, graph, qual)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -393,8 +472,8 @@ class Model:
                                                margin, _ptr(cand), _ptr(margins), _ptr(fell_back),
                                                _stream_handle(stream)))
 
-    def scan(self, index, seq, offsets, K, margin, out, fell_back=None, stream=None):
-        r = _reads_struct(seq, offsets, True)
+    def scan(self, index, seq, offsets, K, margin, out, fell_back=None, stream=None, qual=None):
+        r = _reads_struct(seq, offsets, True, qual)
         _check(lib().maxss_scan_reads_proposed(h_(index), self.handle, ctypes.byref(r), K, margin,
                                                _ptr(out), _ptr(fell_back),
                                                _stream_handle(stream)))
@@ -428,26 +507,27 @@ class Index:
     """Owner of a genome index (freed on close / garbage collection)."""
 
     def __init__(self, genome, frag_len: int, max_read_len: int, match: int = 1,
-                 mismatch: int = -1, gap: int = -2, flags: int = 0):
+                 mismatch: int = -1, gap: int = -2, flags: int = 0, qual_scale: int = 0):
         self.handle = maxss_index_genome(genome, frag_len, max_read_len, match, mismatch, gap,
-                                         flags)
+                                         flags, qual_scale)
         self.G, self.NF, self.F = maxss_index_info(self.handle)
         self.max_read_len = max_read_len
-        self.params = dict(match=match, mismatch=mismatch, gap=gap, flags=flags)
+        self.params = dict(match=match, mismatch=mismatch, gap=gap, flags=flags,
+                           qual_scale=qual_scale)
 
-    def scan(self, seq, offsets, out=None, stream=None):
-        return maxss_scan_reads(self.handle, seq, offsets, out, stream)
+    def scan(self, seq, offsets, out=None, stream=None, qual=None):
+        return maxss_scan_reads(self.handle, seq, offsets, out, stream, qual)
 
     def align(self, seq, offsets, top, pad: int = 100, cigar_stride: int = 512, out=None,
-              cigar=None, stream=None):
+              cigar=None, stream=None, qual=None):
         return maxss_align_top(self.handle, seq, offsets, top, pad, cigar_stride, out, cigar,
-                               stream)
+                               stream, qual)
 
     def set_tiles(self, np_: int = 0, reads_per_tile: int = 0, rounds: int = 0):
         maxss_index_set_tiles(self.handle, np_, reads_per_tile, rounds)
 
-    def autotune(self, seq, offsets, cache_path=None):
-        return maxss_autotune(self.handle, seq, offsets, cache_path)
+    def autotune(self, seq, offsets, cache_path=None, qual=None):
+        return maxss_autotune(self.handle, seq, offsets, cache_path, qual)
 
     def close(self):
         if getattr(self, "handle", None):

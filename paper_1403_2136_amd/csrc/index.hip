@@ -6,6 +6,7 @@
 // global memory access").  On the device the genome is kept 2-bit packed with
 // a separate N mask (the scan stages it into LDS) and as one code byte per
 // position (the second phase and the winners' re-scan read it).
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -62,7 +63,20 @@ maxss_status validate_host_reads(const Index* ix, const maxss_reads* r) {
       if (host_code(r->seq[k]) == 0xFF)
         return fail(MAXSS_EINVAL, "read %u: invalid character 0x%02x at %llu", i,
                     (unsigned)(unsigned char)r->seq[k], (unsigned long long)(k - a));
+    if (qual_mode(ix) && r->qual)
+      for (uint64_t k = a; k < b; k++) {
+        const int c = (unsigned char)r->qual[k];
+        if (c < 33 || c > 126)
+          return fail(MAXSS_EINVAL, "read %u: quality 0x%02x at %llu outside '!'..'~'", i,
+                      (unsigned)c, (unsigned long long)(k - a));
+      }
   }
+  return MAXSS_OK;
+}
+
+maxss_status require_quals(const Index* ix, const maxss_reads* r) {
+  if (qual_mode(ix) && r->n && !r->qual)
+    return fail(MAXSS_EINVAL, "the index scores with base qualities: reads need `qual`");
   return MAXSS_OK;
 }
 
@@ -71,6 +85,7 @@ maxss_status stage_reads(const maxss_reads* r, hipStream_t st, DeviceReads* d) {
   if (r->on_device) {
     d->seq = r->seq;
     d->off = r->offsets;
+    d->qual = r->qual;
     return MAXSS_OK;
   }
   uint64_t a = r->offsets[0], b = r->offsets[r->n];
@@ -91,6 +106,14 @@ maxss_status stage_reads(const maxss_reads* r, hipStream_t st, DeviceReads* d) {
                                     hipMemcpyHostToDevice, st),
                      "copy offsets")))
     return s;
+  if (r->qual) {
+    if ((s = check_hip(hipMallocAsync((void**)&d->own_qual, bytes ? bytes : 1, st),
+                       "hipMallocAsync(qualities)")) ||
+        (s = check_hip(hipMemcpyAsync(d->own_qual, r->qual + a, bytes, hipMemcpyHostToDevice, st),
+                       "copy qualities")))
+      return s;
+    d->qual = d->own_qual;
+  }
   // the host vector dies at return: make the copy complete first
   if ((s = check_hip(hipStreamSynchronize(st), "sync after read upload"))) return s;
   d->seq = d->own_seq;
@@ -101,8 +124,10 @@ maxss_status stage_reads(const maxss_reads* r, hipStream_t st, DeviceReads* d) {
 void release_reads(DeviceReads* d, hipStream_t st) {
   if (d->own_seq) (void)hipFreeAsync(d->own_seq, st);
   if (d->own_off) (void)hipFreeAsync(d->own_off, st);
+  if (d->own_qual) (void)hipFreeAsync(d->own_qual, st);
   d->own_seq = nullptr;
   d->own_off = nullptr;
+  d->own_qual = nullptr;
 }
 
 // ----------------------------------------------------------- kernel timing
@@ -160,8 +185,9 @@ __device__ inline uint32_t pool_shift_code(uint8_t q) { return q == kN ? 4u : 2u
 // (N past the end).
 __global__ __launch_bounds__(256) void encode_reads_kernel(
     const char* __restrict__ seq, const uint64_t* __restrict__ off, uint32_t n,
-    uint32_t max_len, uint32_t mstride, uint32_t* __restrict__ sel4,
-    uint8_t* __restrict__ codes, uint32_t* __restrict__ lens) {
+    uint32_t max_len, uint32_t mstride, uint32_t step, uint32_t* __restrict__ sel4,
+    uint8_t* __restrict__ codes, uint32_t* __restrict__ lens, const char* __restrict__ qual,
+    QualTable qt, uint16_t* __restrict__ qsc) {
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t lane = threadIdx.x & 63;
   if (wave >= n) return;
@@ -171,7 +197,24 @@ __global__ __launch_bounds__(256) void encode_reads_kernel(
   const uint32_t m = ok ? (uint32_t)len64 : 0;
   bool bad = false;
   for (uint32_t k = lane; k < m; k += 64) bad |= dev_code(seq[a + k]) == 0xFF;
+  if (qsc)
+    for (uint32_t k = lane; k < m; k += 64) {
+      const int c = (unsigned char)qual[a + k];
+      bad |= c < 33 || c > 126;
+    }
   ok = ok && !__any(bad);
+  if (qsc) {
+    // per position: (match, mismatch) of its quality, in read order
+    uint16_t* qr = qsc + (uint64_t)wave * mstride;
+    for (uint32_t k = lane; k < mstride; k += 64) {
+      uint16_t v = 0;
+      if (ok && k < m) {
+        const int q = (unsigned char)qual[a + k] - 33;
+        v = (uint16_t)((uint8_t)qt.sm[q] | ((uint16_t)(uint8_t)qt.sx[q] << 8));
+      }
+      qr[k] = v;
+    }
+  }
   const uint32_t nw = mstride / 8;
   uint32_t* sf = sel4 + (uint64_t)wave * 2 * nw;
   uint32_t* sr = sf + nw;
@@ -180,15 +223,19 @@ __global__ __launch_bounds__(256) void encode_reads_kernel(
     uint32_t wf = 0, wr = 0;
     for (uint32_t t = 0; t < 8; t++) {
       const uint32_t k = 8 * w + t;
+      // the read as given (second phase, re-scan)
+      cf[k] = (ok && k < m) ? dev_code(seq[a + k]) : kN;
+      // first-phase codes: position step*k of each strand (every other
+      // base with step 2)
+      const uint32_t kk = step * k;
       uint8_t qf = kN, qr = kN;
-      if (ok && k < m) {
-        qf = dev_code(seq[a + k]);
-        const uint8_t c = dev_code(seq[a + (m - 1 - k)]);
+      if (ok && kk < m) {
+        qf = dev_code(seq[a + kk]);
+        const uint8_t c = dev_code(seq[a + (m - 1 - kk)]);
         qr = c == kN ? kN : (uint8_t)(3 - c);  // complement: A<->T, C<->G
       }
       wf |= pool_shift_code(qf) << (4 * t);
       wr |= pool_shift_code(qr) << (4 * t);
-      cf[k] = qf;
     }
     sf[w] = wf;
     sr[w] = wr;
@@ -201,6 +248,11 @@ static constexpr uint32_t kSlack = 64;
 maxss_status alloc_encoded(const Index* ix, uint32_t n, hipStream_t st, EncodedReads* e) {
   e->mstride = read_stride(ix);
   maxss_status s;
+  if (qual_mode(ix) &&
+      (s = check_hip(hipMallocAsync((void**)&e->qsc, sizeof(uint16_t) * ((uint64_t)n * e->mstride +
+                                                                         kSlack), st),
+                     "hipMallocAsync(position scores)")))
+    return s;
   if ((s = check_hip(hipMallocAsync((void**)&e->sel4,
                                     sizeof(uint32_t) * ((uint64_t)n * 2 * (e->mstride / 8) + kSlack),
                                     st),
@@ -218,8 +270,15 @@ maxss_status encode_reads_into(const Index* ix, const DeviceReads& r, hipStream_
   const uint64_t n = r.n;
   const uint32_t blocks = (uint32_t)((n * 64 + 255) / 256);
   ProfScope prof("encode", st);
+  const uint32_t step = (ix->p.flags & MAXSS_FAST) ? 2u : 1u;
+  QualTable qt;
+  memcpy(qt.sm, ix->qsm, sizeof(qt.sm));
+  memcpy(qt.sx, ix->qsx, sizeof(qt.sx));
+  // position scores only where both the buffer and the qualities exist (a
+  // proposal-only call encodes reads without qualities)
+  uint16_t* qsc = (qual_mode(ix) && r.qual) ? e.qsc : nullptr;
   encode_reads_kernel<<<blocks, 256, 0, st>>>(r.seq, r.off, r.n, ix->p.max_read_len, e.mstride,
-                                              e.sel4, e.codes, e.lens);
+                                              step, e.sel4, e.codes, e.lens, r.qual, qt, qsc);
   return check_hip(hipGetLastError(), "encode_reads_kernel");
 }
 
@@ -227,9 +286,11 @@ void release_encoded(EncodedReads* e, hipStream_t st) {
   if (e->sel4) (void)hipFreeAsync(e->sel4, st);
   if (e->codes) (void)hipFreeAsync(e->codes, st);
   if (e->lens) (void)hipFreeAsync(e->lens, st);
+  if (e->qsc) (void)hipFreeAsync(e->qsc, st);
   e->sel4 = nullptr;
   e->codes = nullptr;
   e->lens = nullptr;
+  e->qsc = nullptr;
 }
 
 }  // namespace maxss
@@ -253,8 +314,18 @@ extern "C" maxss_status maxss_index_genome(const char* seq, uint64_t len,
   if ((uint64_t)p.max_read_len * (uint64_t)p.match > 65535u)
     return fail(MAXSS_EINVAL, "max_read_len * match = %llu exceeds 65535",
                 (unsigned long long)p.max_read_len * p.match);
-  if (p.flags & ~(MAXSS_ONE_STRAND | MAXSS_NW_GLOBAL))
+  if (p.flags & ~(MAXSS_ONE_STRAND | MAXSS_NW_GLOBAL | MAXSS_FAST))
     return fail(MAXSS_EINVAL, "unknown flags 0x%x", p.flags);
+  if (p.qual_scale > 0) {
+    // every position score must fit the scan's int8 score pool, and a whole
+    // read its 16-bit exact range
+    if ((int64_t)p.match * p.qual_scale > 127 || -(int64_t)p.mismatch * p.qual_scale > 381)
+      return fail(MAXSS_EINVAL, "match*qual_scale <= 127 and -mismatch*qual_scale <= 381 needed");
+    if ((uint64_t)p.max_read_len * (uint64_t)p.match * p.qual_scale > 65535u)
+      return fail(MAXSS_EINVAL, "max_read_len * match * qual_scale exceeds 65535");
+    if ((int64_t)p.gap * p.qual_scale < -1000000000ll)
+      return fail(MAXSS_EINVAL, "gap * qual_scale too large");
+  }
   const uint64_t F = p.frag_len;
   const uint64_t NF64 = (len + F - 1) / F;
   if (NF64 >= (1ull << 31) || F >= (1u << 30))
@@ -270,6 +341,13 @@ extern "C" maxss_status maxss_index_genome(const char* seq, uint64_t len,
   ix->F = (uint32_t)F;
   ix->NF = (uint32_t)NF64;
   ix->p = p;
+  if (p.qual_scale > 0)
+    for (int q = 0; q < 94; q++) {
+      // x = 1 - 10^(-q/10), the probability that the base is right
+      const double x = 1.0 - pow(10.0, -(double)q / 10.0);
+      ix->qsm[q] = (int8_t)lround((double)p.match * x * (double)p.qual_scale);
+      ix->qsx[q] = (int8_t)lround((double)p.mismatch * x * (double)p.qual_scale / 3.0);
+    }
   // Room past the last fragment: a full window (max_read_len-1), the widest
   // scan tile's second half and staging tail, and the NW padding.
   uint64_t tail = 2ull * 128 * 32 + ((p.max_read_len + 63u) & ~63u) + 1024;

@@ -38,7 +38,18 @@ struct Index {
   uint32_t* g2 = nullptr;
   uint32_t* nmask = nullptr;
   uint8_t* codes = nullptr;
+  // position-specific scores by Phred quality (qual_scale > 0): match, mismatch
+  int8_t qsm[94] = {};
+  int8_t qsx[94] = {};
 };
+
+// The per-quality score pairs as a kernel argument.
+struct QualTable {
+  int8_t sm[94];
+  int8_t sx[94];
+};
+
+inline bool qual_mode(const Index* ix) { return ix->p.qual_scale > 0; }
 
 // Thread-local error message + status helper.
 maxss_status fail(maxss_status st, const char* fmt, ...);
@@ -50,6 +61,14 @@ maxss_status check_hip(hipError_t e, const char* what);
 // Host-side ASCII -> code, 0xFF for a character outside ACGTN/acgtn.
 uint8_t host_code(char c);
 
+// Read positions advanced per first-phase Kadane step: 2 when every other
+// base is scored (MAXSS_FAST), else 1.
+inline uint32_t scan_step(const Index* ix) { return (ix->p.flags & MAXSS_FAST) ? 2u : 1u; }
+
+// Window start offsets of one parity class in a fragment (F / step; F is a
+// multiple of 16).
+inline uint32_t parity_offsets(const Index* ix) { return ix->F / scan_step(ix); }
+
 // Padded read-profile stride (positions per read per strand) for an index.
 inline uint32_t read_stride(const Index* ix) { return (ix->p.max_read_len + 63u) & ~63u; }
 
@@ -57,10 +76,15 @@ inline uint32_t read_stride(const Index* ix) { return (ix->p.max_read_len + 63u)
 struct DeviceReads {
   const char* seq = nullptr;
   const uint64_t* off = nullptr;
+  const char* qual = nullptr;    // Phred+33 qualities laid out as seq, or null
   uint32_t n = 0;
   char* own_seq = nullptr;       // set when the library uploaded host reads
   uint64_t* own_off = nullptr;
+  char* own_qual = nullptr;
 };
+
+// EINVAL when the index scores with base qualities and the reads carry none.
+maxss_status require_quals(const Index* ix, const maxss_reads* r);
 
 // Validate host reads (length and characters).  MAXSS_OK or an error status.
 maxss_status validate_host_reads(const Index* ix, const maxss_reads* r);
@@ -81,6 +105,9 @@ struct EncodedReads {
   uint32_t* sel4 = nullptr;  // [n][2][mstride/8]
   uint8_t* codes = nullptr;  // [n][mstride]
   uint32_t* lens = nullptr;  // [n]
+  // [n][mstride] per read position (forward orientation): match score in the
+  // low byte, mismatch score in the high byte (int8 each); quality mode only
+  uint16_t* qsc = nullptr;
   uint32_t mstride = 0;
 };
 

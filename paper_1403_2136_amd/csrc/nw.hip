@@ -26,6 +26,7 @@ struct NwArgs {
   uint64_t G;
   uint32_t F, NF;
   const uint8_t* rcodes;  // forward read codes [n][mstride]
+  const uint16_t* qsc;    // quality mode: [n][mstride] (match | mismatch << 8), else null
   const uint32_t* lens;
   uint32_t mstride;
   const maxss_top2* top;
@@ -112,6 +113,14 @@ __global__ __launch_bounds__(kNwThreads) void nw_kernel(NwArgs a) {
     const uint32_t j0 = 1 + tid * a.cw;  // first column of this thread
     for (uint32_t r = 1; r <= m; r++) {
       const uint8_t q = lq[r - 1];
+      // this row's match / mismatch: the read base's own pair in quality mode
+      // (strand 1 rows run over the read backwards)
+      int Mr = a.M, Xr = a.X;
+      if (a.qsc) {
+        const uint16_t v = a.qsc[(uint64_t)i * a.mstride + (strand ? m - r : r - 1)];
+        Mr = (int)(int8_t)(v & 0xFFu);
+        Xr = (int)(int8_t)(v >> 8);
+      }
       const int col0 = (int)r * a.gap;
       // pass 1: this thread's running max of T[j] + j*g
       long long run = LLONG_MIN;
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(kNwThreads) void nw_kernel(NwArgs a) {
         const uint32_t j = j0 + t;
         if (j > ncols) break;
         const uint8_t gc = lg[j - 1];
-        const int d = prev[j - 1] + ((q == gc && q != kN) ? a.M : a.X);
+        const int d = prev[j - 1] + ((q == gc && q != kN) ? Mr : Xr);
         const int u = prev[j] + a.gap;
         const long long tv = (long long)(d > u ? d : u) + (long long)j * g;
         run = tv > run ? tv : run;
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(kNwThreads) void nw_kernel(NwArgs a) {
         uint32_t mv = 0;
         if (j <= ncols) {
           const uint8_t gc = lg[j - 1];
-          const int d = prev[j - 1] + ((q == gc && q != kN) ? a.M : a.X);
+          const int d = prev[j - 1] + ((q == gc && q != kN) ? Mr : Xr);
           const int u = prev[j] + a.gap;
           const long long tv = (long long)(d > u ? d : u) + (long long)j * g;
           carry = tv > carry ? tv : carry;
@@ -269,8 +278,12 @@ maxss_status nw_pipeline(const Index* ix, const EncodedReads& er, uint32_t n,
   NwArgs a{};
   a.gcodes = ix->codes; a.G = ix->G; a.F = ix->F; a.NF = ix->NF;
   a.rcodes = er.codes; a.lens = er.lens; a.mstride = er.mstride;
+  a.qsc = qual_mode(ix) ? er.qsc : nullptr;
+  if (qual_mode(ix) && !er.qsc) return fail(MAXSS_ESTATE, "quality mode without position scores");
   a.top = dtop; a.n = n; a.pad = pad;
-  a.M = ix->p.match; a.X = ix->p.mismatch; a.gap = ix->p.gap;
+  a.M = ix->p.match; a.X = ix->p.mismatch;
+  // in quality mode the gap is in the same 1/qual_scale units as the scores
+  a.gap = qual_mode(ix) ? ix->p.gap * (int)ix->p.qual_scale : ix->p.gap;
   a.global_mode = (ix->p.flags & MAXSS_NW_GLOBAL) ? 1 : 0;
   a.cw = sh.cw; a.rowbytes = sh.rowbytes; a.slab = slab; a.m_max = ix->p.max_read_len;
   a.out = dout; a.cigar = dcig; a.cigar_stride = cigar_stride;
@@ -298,6 +311,7 @@ extern "C" maxss_status maxss_align_top(const maxss_index* index, const maxss_re
   if (!reads->seq || !reads->offsets) return fail(MAXSS_EINVAL, "NULL reads");
   hipStream_t st = (hipStream_t)stream;
   maxss_status s;
+  if ((s = require_quals(ix, reads))) return s;
   if (!reads->on_device && (s = validate_host_reads(ix, reads))) return s;
   int cur = 0;
   if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;

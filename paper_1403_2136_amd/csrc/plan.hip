@@ -55,7 +55,7 @@ static maxss_status check_run_args(Plan* p, const maxss_reads* r, maxss_top2* to
                                       p->capacity);
   if (r->n && (!r->seq || !r->offsets)) return fail(MAXSS_EINVAL, "NULL reads");
   if ((aln == nullptr) != (cig == nullptr)) return fail(MAXSS_EINVAL, "aln and cigar go together");
-  return MAXSS_OK;
+  return require_quals(p->ix, r);
 }
 
 static maxss_status plan_step(Plan* p, const maxss_reads* r, maxss_top2* top, maxss_aln* aln,
@@ -63,6 +63,7 @@ static maxss_status plan_step(Plan* p, const maxss_reads* r, maxss_top2* top, ma
   DeviceReads dr;
   dr.seq = r->seq;
   dr.off = r->offsets;
+  dr.qual = r->qual;
   dr.n = r->n;
   maxss_status s = scan_pipeline(p->ix, dr, top, p->w, nullptr, st);
   if (s || !aln) return s;
@@ -77,7 +78,8 @@ static std::vector<TileOverride> tile_candidates(const Index* ix) {
   const uint32_t rs[3] = {8, 16, 32};
   const uint32_t rounds[3] = {4, 8, 16};
   for (int np : nps) {
-    if (128u * (uint32_t)np > (ix->F > 1024u ? ix->F : 1024u)) continue;  // mostly idle lanes
+    const uint32_t Fp = parity_offsets(ix);
+    if (128u * (uint32_t)np > (Fp > 1024u ? Fp : 1024u)) continue;  // mostly idle lanes
     for (uint32_t R : rs)
       for (uint32_t rd : rounds) c.push_back(TileOverride{np, R, rd});
   }
@@ -233,6 +235,7 @@ extern "C" maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sa
   if (!ix || !sample || !result) return fail(MAXSS_EINVAL, "NULL argument");
   if (sample->n == 0) return fail(MAXSS_EINVAL, "empty sample");
   maxss_status s;
+  if ((s = require_quals(ix, sample))) return s;
   if (!sample->on_device && (s = validate_host_reads(ix, sample))) return s;
   int cur = 0;
   if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;

@@ -80,7 +80,7 @@ struct ScanArgs {
   const uint32_t* lens;
   const uint32_t* order;
   uint32_t n;
-  uint32_t R, ntiles, C, nchunks;
+  uint32_t R, ntiles, nchunks;
   uint32_t total_work;
   uint32_t* work_ctr;
   int4* partial;
@@ -89,6 +89,9 @@ struct ScanArgs {
   const int32_t* cand;  // NULL, or per read K candidate fragments (ascending)
   uint32_t K;
   uint32_t nfe;         // fragments (or candidates) each tile iterates
+  uint32_t step;        // 1, or 2 for the fast scan (every other read base)
+  const uint16_t* qsc;  // quality mode: [n][mp_max] (match | mismatch << 8) per position
+  uint32_t cq;          // LDS words of position-score pairs per read strand
 };
 
 template <int NP>
@@ -120,20 +123,51 @@ __device__ inline uint32_t win_word(const uint32_t* __restrict__ lds, uint32_t l
   return lds[lbase + (x + x / NP)];
 }
 
-// SUB Kadane steps (SUB <= 8) at read positions [k, k+SUB), with the window
-// loaded from LDS for exactly these steps.
-template <int NP, int SUB>
+// The score pool of one step.  Plain scoring: the all-mismatch pool with the
+// read base's byte flipped to the match score.  Quality mode: the same
+// construction from the position's own pair (low byte match, high byte
+// mismatch, int8 each): bytes [X, X, sign(X), X, 0, X, 0, X], then the read
+// base's byte flipped to M.
+template <bool QS>
+__device__ inline uint64_t step_pool(uint32_t c, uint32_t pair, uint64_t xpool, uint64_t dpool) {
+  if constexpr (QS) {
+    const uint32_t sm = pair & 0xFFu, sx = (pair >> 8) & 0xFFu;
+    const uint32_t sg = (sx & 0x80u) ? 0xFFu : 0u;
+    const uint32_t lo = sx | (sx << 8) | (sg << 16) | (sx << 24);
+    const uint32_t hi = (sx << 8) | (sx << 24);
+    const uint64_t xp = ((uint64_t)hi << 32) | lo;
+    return xp ^ ((uint64_t)((sm ^ sx) & 0xFFu) << (c << 3));
+  } else {
+    (void)pair;
+    return xpool ^ (dpool << (c << 3));
+  }
+}
+
+// Pair of scan position t of a block whose pairs were read into qw (two
+// positions per word, the block starting at an even position).
+__device__ inline uint32_t pair_at(const uint32_t* qw, int t) {
+  return (qw[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+}
+
+// SUB Kadane steps (SUB <= 8) at read positions [k, k+SUB) (k even), with the
+// window loaded from LDS for exactly these steps.
+template <int NP, int SUB, bool QS>
 __device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lbase,
-                                  const uint32_t* __restrict__ lc, uint32_t k, uint64_t xpool,
+                                  const uint32_t* __restrict__ lc,
+                                  const uint32_t* __restrict__ lq, uint32_t k, uint64_t xpool,
                                   uint64_t dpool, s16x2 (&H)[NP], s16x2 (&B)[NP]) {
   uint32_t win[NP + SUB - 1];
 #pragma unroll
   for (int i = 0; i < NP + SUB - 1; i++) win[i] = win_word<NP>(lds, lbase, k + i);
   const uint32_t cc = codes8(lc, k);
+  uint32_t qw[(SUB + 1) / 2];
+#pragma unroll
+  for (int i = 0; i < (SUB + 1) / 2; i++)
+    qw[i] = QS ? __builtin_amdgcn_readfirstlane(lq[k / 2 + i]) : 0u;
 #pragma unroll
   for (int t = 0; t < SUB; t++) {
     const uint32_t c = (cc >> (4 * t)) & 15u;
-    const uint64_t pool = xpool ^ (dpool << (c << 3));
+    const uint64_t pool = step_pool<QS>(c, pair_at(qw, t), xpool, dpool);
     const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
 #pragma unroll
     for (int j = 0; j < NP; j++) {
@@ -149,15 +183,18 @@ __device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lba
 // kb..kb+NP-1 of the lane) and second[0..NP) (words kb+NP..kb+2NP-1).
 // first[t] is last read at step t, so right after step t it is reloaded with
 // word kb+2NP+t: the block after next finds it there as its `second` half.
-template <int NP>
+template <int NP, bool QS>
 __device__ inline void kadane_block(uint32_t (&first)[NP], const uint32_t (&second)[NP],
                                     const uint32_t* __restrict__ lw, const uint32_t (&cc)[NP / 8],
-                                    uint64_t xpool, uint64_t dpool, s16x2 (&H)[NP],
-                                    s16x2 (&B)[NP]) {
+                                    const uint32_t* __restrict__ lqb, uint64_t xpool,
+                                    uint64_t dpool, s16x2 (&H)[NP], s16x2 (&B)[NP]) {
+  uint32_t qw[NP / 2];
+#pragma unroll
+  for (int i = 0; i < NP / 2; i++) qw[i] = QS ? __builtin_amdgcn_readfirstlane(lqb[i]) : 0u;
 #pragma unroll
   for (int t = 0; t < NP; t++) {
     const uint32_t c = (cc[t >> 3] >> (4 * (t & 7))) & 15u;
-    const uint64_t pool = xpool ^ (dpool << (c << 3));
+    const uint64_t pool = step_pool<QS>(c, pair_at(qw, t), xpool, dpool);
     const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
 #pragma unroll
     for (int j = 0; j < NP; j++) {
@@ -176,9 +213,10 @@ __device__ inline void kadane_block(uint32_t (&first)[NP], const uint32_t (&seco
 // two register halves that swap roles every block), then the last m % NP
 // steps as unrolled sub-blocks of 8/4/2/1 steps, so no padding step is
 // computed.  Returns the lane's per-pair maxima (biased by -32768) in B.
-template <int NP>
+template <int NP, bool QS>
 __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t lane,
-                                    const uint32_t* __restrict__ lc, uint32_t m,
+                                    const uint32_t* __restrict__ lc,
+                                    const uint32_t* __restrict__ lq, uint32_t m,
                                     uint64_t xpool, uint64_t dpool, s16x2 (&B)[NP]) {
   constexpr int CW = NP / 8;
   s16x2 H[NP];
@@ -210,32 +248,38 @@ __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t l
       for (int i = 0; i < CW; i++) cc[i] = cn[i];
 #pragma unroll
       for (int i = 0; i < CW; i++) cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + NP) / 8 + i]);
-      kadane_block<NP>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, xpool, dpool, H, B);
+      kadane_block<NP, QS>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, lq + kb / 2, xpool,
+                           dpool, H, B);
 #pragma unroll
       for (int i = 0; i < CW; i++) cc[i] = cn[i];
 #pragma unroll
       for (int i = 0; i < CW; i++)
         cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + 2 * NP) / 8 + i]);
-      kadane_block<NP>(wB, wA, lds + lbase + pb + 3 * (NP + 1), cc, xpool, dpool, H, B);
+      kadane_block<NP, QS>(wB, wA, lds + lbase + pb + 3 * (NP + 1), cc, lq + (kb + NP) / 2,
+                           xpool, dpool, H, B);
     }
     if (kb < mfull) {  // one block left
       uint32_t cc[CW];
 #pragma unroll
       for (int i = 0; i < CW; i++) cc[i] = cn[i];
-      kadane_block<NP>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, xpool, dpool, H, B);
+      kadane_block<NP, QS>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, lq + kb / 2, xpool,
+                           dpool, H, B);
     }
   }
   const uint32_t rem = m - mfull;
   uint32_t k = mfull;
   if (NP > 16 && (rem & 16)) {
-    kadane_sub<NP, 8>(lds, lbase, lc, k, xpool, dpool, H, B);
-    kadane_sub<NP, 8>(lds, lbase, lc, k + 8, xpool, dpool, H, B);
+    kadane_sub<NP, 8, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
+    kadane_sub<NP, 8, QS>(lds, lbase, lc, lq, k + 8, xpool, dpool, H, B);
     k += 16;
   }
-  if (NP > 8 && (rem & 8)) { kadane_sub<NP, 8>(lds, lbase, lc, k, xpool, dpool, H, B); k += 8; }
-  if (rem & 4) { kadane_sub<NP, 4>(lds, lbase, lc, k, xpool, dpool, H, B); k += 4; }
-  if (rem & 2) { kadane_sub<NP, 2>(lds, lbase, lc, k, xpool, dpool, H, B); k += 2; }
-  if (rem & 1) kadane_sub<NP, 1>(lds, lbase, lc, k, xpool, dpool, H, B);
+  if (NP > 8 && (rem & 8)) {
+    kadane_sub<NP, 8, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
+    k += 8;
+  }
+  if (rem & 4) { kadane_sub<NP, 4, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B); k += 4; }
+  if (rem & 2) { kadane_sub<NP, 2, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B); k += 2; }
+  if (rem & 1) kadane_sub<NP, 1, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
 }
 
 __device__ inline int wave_max_i32(int v) {
@@ -244,30 +288,36 @@ __device__ inline int wave_max_i32(int v) {
   return v;
 }
 
-template <int NP>
+template <int NP, bool QS>
 __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t HALF = 64u * NP, S = 128u * NP;
   const uint32_t lane = threadIdx.x;
   uint32_t* lcodes = lds + a.win_slots;
+  uint32_t* lqs = lcodes + a.R * 2 * a.cw;  // quality mode: position-score pairs
   for (;;) {
     uint32_t w = 0;
     if (lane == 0) w = atomicAdd(a.work_ctr, 1u);
     w = __builtin_amdgcn_readfirstlane(__shfl(w, 0, 64));
     if (w >= a.total_work) break;
-    // chunk-major order: every tile of chunk 0, then chunk 1, ...; the last
-    // (shortest) chunk and, within a chunk, the shortest tiles come last
-    const uint32_t chunk = w / a.ntiles, tile = w - chunk * a.ntiles;
+    // tile-major order over the length-sorted tiles: every chunk of the
+    // longest tile first, the shortest tiles' chunks last.  Chunks are
+    // balanced (sizes differ by at most one fragment), so the items come in
+    // nonincreasing cost and the last ones to start are the cheapest.
+    const uint32_t tile = w / a.nchunks, chunk = w - tile * a.nchunks;
     const uint32_t rbase = tile * a.R;
     const uint32_t rcount = min(a.R, a.n - rbase);
     const uint32_t my_read = lane < rcount ? a.order[rbase + lane] : 0u;
-    const uint32_t my_len = lane < rcount ? a.lens[my_read] : 0u;
+    // Kadane steps of the read: its length, or half of it rounded up when
+    // every other base is scored
+    const uint32_t my_len = lane < rcount ? (a.lens[my_read] + a.step - 1) / a.step : 0u;
     const uint32_t my_mp = (my_len + NP - 1) / NP * NP;
     const uint32_t mp_tile = (uint32_t)wave_max_i32((int)my_mp);
     const uint32_t nwords = staged_words<NP>(mp_tile);
     if (mp_tile == 0) continue;  // a tile of skipped reads (length 0)
     int t1s = -1, t1f = -1, t2s = -1, t2f = -1;
-    const uint32_t f0 = chunk * a.C, f1 = min(a.nfe, f0 + a.C);
+    const uint32_t f0 = (uint32_t)((uint64_t)chunk * a.nfe / a.nchunks);
+    const uint32_t f1 = (uint32_t)((uint64_t)(chunk + 1) * a.nfe / a.nchunks);
     // candidate mode: one read per tile, fragments from its sorted list
     const int32_t* clist =
         a.cand ? a.cand + (uint64_t)__builtin_amdgcn_readfirstlane(my_read) * a.K : nullptr;
@@ -279,29 +329,55 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
       const uint32_t rid = a.order[rbase + r];
       lcodes[idx] = wd < a.cwg ? a.sel4[((uint64_t)rid * 2 + s) * a.cwg + wd] : 0x44444444u;
     }
+    if constexpr (QS) {
+      // position-score pairs of the scanned positions, two per word; strand
+      // 1 reads the read's pairs backwards
+      for (uint32_t idx = lane; idx < rcount * 2 * a.cq; idx += 64) {
+        const uint32_t r = idx / (2 * a.cq), rem = idx - r * 2 * a.cq;
+        const uint32_t s = rem / a.cq, wd = rem - s * a.cq;
+        const uint32_t rid = a.order[rbase + r];
+        const uint32_t mfull = a.lens[rid];
+        const uint16_t* qr = a.qsc + (uint64_t)rid * a.mp_max;
+        uint32_t v = 0;
+#pragma unroll
+        for (uint32_t h = 0; h < 2; h++) {
+          const uint32_t kk = a.step * (2 * wd + h);  // position in the strand
+          if (kk < mfull) v |= (uint32_t)qr[s ? mfull - 1 - kk : kk] << (16 * h);
+        }
+        lqs[idx] = v;
+      }
+    }
     for (uint32_t fi = f0; fi < f1; fi++) {
       const uint32_t f = clist ? (uint32_t)clist[fi] : fi;
       int fv = -1;  // lane r: value of fragment f for read r
-      for (uint32_t seg = 0; seg < a.nseg; seg++) {
-        const uint64_t base = (uint64_t)f * a.F + (uint64_t)seg * S;
+      // A segment holds S offsets of each parity class: with step 1 the
+      // offsets seg*S + x, with step 2 the offsets seg*2S + par + 2x.  The
+      // window word x of a parity is the genome at base + step*x, so one
+      // Kadane step still advances the window by one LDS word.
+      for (uint32_t sp = 0; sp < a.nseg * a.step; sp++) {
+        const uint32_t seg = sp / a.step, par = sp - seg * a.step;
+        const uint64_t base = (uint64_t)f * a.F + (uint64_t)seg * S * a.step + par;
         __syncthreads();  // previous segment's readers are done with LDS
         for (uint32_t wd = lane; wd < nwords; wd += 64) {
-          const uint64_t P = base + wd;
+          const uint64_t P = base + (uint64_t)a.step * wd;
           const uint32_t c0 = genome_code(a.g2, a.nmask, a.Lpad, P);
-          const uint32_t c1 = genome_code(a.g2, a.nmask, a.Lpad, P + HALF);
+          const uint32_t c1 = genome_code(a.g2, a.nmask, a.Lpad, P + (uint64_t)a.step * HALF);
           lds[phys<NP>(wd)] = sel16(c0) | (sel16(c1) << 16);
         }
         __syncthreads();
-        const bool partial_seg = (uint64_t)(seg + 1) * S > a.F;
-        const int lo_cnt = min(max((int)a.F - (int)(seg * S) - (int)(lane * NP), 0), NP);
-        const int hi_cnt = min(max((int)a.F - (int)(seg * S + HALF) - (int)(lane * NP), 0), NP);
+        // offsets of this parity left in the fragment from the segment start
+        const int left = ((int)a.F - (int)(seg * S * a.step + par) + (int)a.step - 1) / (int)a.step;
+        const bool partial_seg = left < (int)S;
+        const int lo_cnt = min(max(left - (int)(lane * NP), 0), NP);
+        const int hi_cnt = min(max(left - (int)HALF - (int)(lane * NP), 0), NP);
         for (uint32_t r = 0; r < rcount; r++) {
           const uint32_t m = __builtin_amdgcn_readlane(my_len, r);
           if (m == 0) continue;
           uint32_t bm = 0x80008000u;
           for (uint32_t s = 0; s < a.nstrands; s++) {
             s16x2 B[NP];
-            kadane_pairs<NP>(lds, lane, lcodes + (r * 2 + s) * a.cw, m, a.xpool, a.dpool, B);
+            kadane_pairs<NP, QS>(lds, lane, lcodes + (r * 2 + s) * a.cw,
+                                 lqs + (r * 2 + s) * a.cq, m, a.xpool, a.dpool, B);
             if (partial_seg) {
 #pragma unroll
               for (int j = 0; j < NP; j++) {
@@ -451,10 +527,11 @@ __global__ void merge_kernel(const int4* __restrict__ partial, uint32_t nchunks,
 // Exact re-scan of one winning fragment of one read (int32, one offset per
 // thread and strand) to find its representative window: the smallest strand,
 // then the smallest offset, among the windows reaching the fragment's value.
+// With step 2 only read positions 0, 2, 4, ... of each strand are scored.
 __global__ __launch_bounds__(256) void rescan_kernel(
     const uint8_t* __restrict__ gcodes, uint32_t F, const uint8_t* __restrict__ rcodes,
     const uint32_t* __restrict__ lens, uint32_t mstride, int M, int X, uint32_t nstrands,
-    uint32_t n, maxss_top2* __restrict__ out) {
+    uint32_t step, const uint16_t* __restrict__ qsc, uint32_t n, maxss_top2* __restrict__ out) {
   extern __shared__ uint8_t sh[];
   const uint32_t i = blockIdx.x, which = blockIdx.y;
   const uint32_t m = lens[i];
@@ -462,6 +539,8 @@ __global__ __launch_bounds__(256) void rescan_kernel(
   if (m == 0 || f < 0) return;
   uint8_t* lg = sh;                    // F + m - 1 genome codes
   uint8_t* lq = sh + F + mstride;      // 2*m read codes: forward, reverse complement
+  // quality mode: 2*m position-score pairs in the same two orientations
+  uint16_t* lp = (uint16_t*)(sh + ((F + 3 * mstride + 3) & ~3u));
   const uint64_t gb = (uint64_t)f * F;
   for (uint32_t t = threadIdx.x; t < F + m - 1; t += blockDim.x) lg[t] = gcodes[gb + t];
   const uint8_t* rc = rcodes + (uint64_t)i * mstride;
@@ -469,6 +548,11 @@ __global__ __launch_bounds__(256) void rescan_kernel(
     uint8_t c = rc[k];
     lq[k] = c;
     lq[m + (m - 1 - k)] = c == kN ? kN : (uint8_t)(3 - c);
+    if (qsc) {
+      const uint16_t v = qsc[(uint64_t)i * mstride + k];
+      lp[k] = v;
+      lp[m + (m - 1 - k)] = v;
+    }
   }
   __syncthreads();
   uint64_t best = 0;
@@ -476,9 +560,14 @@ __global__ __launch_bounds__(256) void rescan_kernel(
     const uint8_t* q = lq + s * m;
     for (uint32_t o = threadIdx.x; o < F; o += blockDim.x) {
       int H = 0, B = 0;
-      for (uint32_t k = 0; k < m; k++) {
+      for (uint32_t k = 0; k < m; k += step) {
         const uint8_t g = lg[o + k], c = q[k];
-        H += (g == c && c != kN) ? M : X;
+        if (qsc) {
+          const uint16_t v = lp[s * m + k];
+          H += (g == c && c != kN) ? (int)(int8_t)(v & 0xFFu) : (int)(int8_t)(v >> 8);
+        } else {
+          H += (g == c && c != kN) ? M : X;
+        }
         H = max(H, 0);
         B = max(B, H);
       }
@@ -504,42 +593,52 @@ __global__ __launch_bounds__(256) void rescan_kernel(
 
 struct Tiles {
   int NP;
-  uint32_t R, ntiles, C, nchunks, nseg, grid;
-  uint32_t win_slots, cw;
+  bool qs;                 // quality mode (position-specific scores)
+  uint32_t R, ntiles, nchunks, nseg, grid;
+  uint32_t win_slots, cw, cq;
   size_t lds;
 };
 
-template <int NP>
+template <int NP, bool QS>
 static maxss_status launch_scan(const ScanArgs& a, uint32_t grid, size_t lds, hipStream_t st) {
   if (lds > 65536) {
-    maxss_status s = check_hip(hipFuncSetAttribute((const void*)scan_kernel<NP>,
+    maxss_status s = check_hip(hipFuncSetAttribute((const void*)scan_kernel<NP, QS>,
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    (int)lds),
                                "hipFuncSetAttribute(scan_kernel)");
     if (s) return s;
   }
   ProfScope prof("scan", st);
-  scan_kernel<NP><<<grid, 64, lds, st>>>(a);
+  scan_kernel<NP, QS><<<grid, 64, lds, st>>>(a);
   return check_hip(hipGetLastError(), "scan_kernel");
 }
 
 // Resident scan waves per CU for (NP, LDS bytes), queried once per shape and
 // cached, so that a step being captured into a graph makes no runtime query.
-static int occupancy_for(int NP, size_t lds) {
+template <int NP, bool QS>
+static hipError_t occupancy_query(int* blocks, size_t lds) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, scan_kernel<NP, QS>, 64, lds);
+}
+
+static int occupancy_for(int NP, bool qs, size_t lds) {
   static std::mutex mu;
   static std::map<std::pair<int, size_t>, int> cache;
   std::lock_guard<std::mutex> g(mu);
-  auto it = cache.find({NP, lds});
+  const int key = NP * 2 + (qs ? 1 : 0);
+  auto it = cache.find({key, lds});
   if (it != cache.end()) return it->second;
   int blocks = 0;
   hipError_t e;
-  switch (NP) {
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_kernel<8>, 64, lds); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_kernel<16>, 64, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_kernel<32>, 64, lds); break;
+  switch (key) {
+    case 16: e = occupancy_query<8, false>(&blocks, lds); break;
+    case 17: e = occupancy_query<8, true>(&blocks, lds); break;
+    case 32: e = occupancy_query<16, false>(&blocks, lds); break;
+    case 33: e = occupancy_query<16, true>(&blocks, lds); break;
+    case 64: e = occupancy_query<32, false>(&blocks, lds); break;
+    default: e = occupancy_query<32, true>(&blocks, lds); break;
   }
   if (e != hipSuccess || blocks < 1) blocks = 1;
-  cache[{NP, lds}] = blocks;
+  cache[{key, lds}] = blocks;
   return blocks;
 }
 
@@ -547,7 +646,7 @@ static int occupancy_for(int NP, size_t lds) {
 static constexpr size_t kScanLdsBudget = 40 * 1024;
 
 static int np_for(const Index* ix, const TileOverride* force) {
-  const uint32_t F = ix->F;
+  const uint32_t F = parity_offsets(ix);
   if (force && (force->NP == 8 || force->NP == 16 || force->NP == 32)) return force->NP;
   if (F % 4096 == 0) return 32;
   if (F % 2048 == 0) return 16;
@@ -564,27 +663,29 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
   Tiles t{};
   t.NP = np_for(ix, force);
   const uint32_t S = 128u * t.NP;
-  t.nseg = (ix->F + S - 1) / S;
+  t.nseg = (parity_offsets(ix) + S - 1) / S;
   t.win_slots = win_slots_for(t.NP, mstride);
   t.cw = mstride / 8 + (uint32_t)t.NP / 8 + 1;
+  t.qs = qual_mode(ix);
+  t.cq = t.qs ? (mstride / scan_step(ix) + 1) / 2 + 1 : 0u;
   const size_t win_bytes = (size_t)t.win_slots * 4u;
-  const size_t per_read = (size_t)2 * t.cw * 4u;
+  const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
   uint32_t rmax = 32;
   while (rmax > 1 && win_bytes + rmax * per_read > kScanLdsBudget) rmax /= 2;
   if (win_bytes + rmax * per_read > 64 * 1024 && rmax > 1) rmax = 1;
   t.R = force->R ? (force->R < rmax ? force->R : rmax) : rmax;
   t.lds = win_bytes + t.R * per_read;
-  const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.lds);
+  const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.lds);
   if (!force->R)
     while (t.R > 4 && (uint64_t)((n + t.R - 1) / t.R) * ix->NF < 4ull * resident) t.R /= 2;
   t.lds = win_bytes + t.R * per_read;
   t.ntiles = (n + t.R - 1) / t.R;
-  // Chunk count: items of equal cost run in rounds of `resident` waves, so
-  // pick the count whose item total best fills whole rounds (at least
-  // `rounds` rounds when the work allows it; fewer, larger items on ties).
+  // Chunk count: the fragments are cut into nchunks balanced chunks, so all
+  // items of a tile cost the same and a uniform read mix runs in rounds of
+  // `resident` waves.  Pick the count whose item total best fills whole
+  // rounds (at least `rounds` rounds when the work allows it; fewer chunks
+  // on ties).
   const uint32_t rounds = force->rounds ? force->rounds : 8;
-  uint32_t best_c = 1;
-  double best_eff = -1.0;
   const uint64_t min_items = (uint64_t)rounds * resident;
   uint64_t c_lo64 = (min_items + t.ntiles - 1) / t.ntiles;
   if (c_lo64 < 1) c_lo64 = 1;
@@ -597,21 +698,18 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
     else if (c_hi > cmax) c_hi = (uint32_t)cmax;
     if (c_lo > c_hi) c_lo = c_hi;
   }
+  uint32_t best_c = c_lo;
+  double best_eff = -1.0;
   for (uint32_t c = c_lo; c <= c_hi; c++) {
-    const uint32_t C = (ix->NF + c - 1) / c;
-    const uint32_t nch = (ix->NF + C - 1) / C;
-    const double full = (double)t.ntiles * (nch - 1) * C +
-                        (double)t.ntiles * (ix->NF - (uint64_t)(nch - 1) * C);
-    const double per_wave = full / resident;
-    const double rnd = std::ceil(per_wave / C - 1e-9);
-    const double eff = per_wave / (rnd * C);
+    const uint64_t items = (uint64_t)t.ntiles * c;
+    const uint64_t nround = (items + resident - 1) / resident;
+    const double eff = (double)items / ((double)nround * resident);
     if (eff > best_eff + 1e-3) {
       best_eff = eff;
-      best_c = nch;
+      best_c = c;
     }
   }
-  t.C = (ix->NF + best_c - 1) / best_c;
-  t.nchunks = (ix->NF + t.C - 1) / t.C;
+  t.nchunks = best_c;
   const uint64_t total = (uint64_t)t.ntiles * t.nchunks;
   t.grid = (uint32_t)(total < resident ? total : resident);
   if (t.grid < 1) t.grid = 1;
@@ -650,6 +748,10 @@ maxss_status alloc_scan_work(const Index* ix, uint32_t n, uint64_t partial_cap, 
       (s = check_hip(hipMalloc((void**)&w->ctr, sizeof(uint32_t)), "alloc counter")) ||
       (s = check_hip(hipMalloc((void**)&w->partial, sizeof(int4) * partial_cap), "alloc partial")))
     return s;
+  if (qual_mode(ix) &&
+      (s = check_hip(hipMalloc((void**)&w->er.qsc, sizeof(uint16_t) * ((uint64_t)n * w->er.mstride + 64)),
+                     "alloc position scores")))
+    return s;
   return MAXSS_OK;
 }
 
@@ -666,6 +768,7 @@ void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st) {
     if (w->er.sel4) (void)hipFree(w->er.sel4);
     if (w->er.codes) (void)hipFree(w->er.codes);
     if (w->er.lens) (void)hipFree(w->er.lens);
+    if (w->er.qsc) (void)hipFree(w->er.qsc);
     w->er = EncodedReads{};
   }
   w->order = w->hist = w->ctr = nullptr;
@@ -687,16 +790,15 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   if (cand) {
     // one read per tile; enough candidate chunks to fill the resident waves
     t.R = 1;
-    const size_t per_read = (size_t)2 * t.cw * 4u;
+    const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
     t.lds = (size_t)t.win_slots * 4u + per_read;
-    const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.lds);
+    const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.lds);
     t.ntiles = n;
     uint64_t want = (8ull * resident + n - 1) / n;
     if (want < 1) want = 1;
     if (want > Kc) want = Kc;
     if (want * n > w.partial_cap) want = w.partial_cap / n ? w.partial_cap / n : 1;
-    t.C = (uint32_t)((Kc + want - 1) / want);
-    t.nchunks = (Kc + t.C - 1) / t.C;
+    t.nchunks = (uint32_t)want;
     const uint64_t total = (uint64_t)t.ntiles * t.nchunks;
     t.grid = (uint32_t)(total < resident ? total : resident);
   }
@@ -722,24 +824,41 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   a.sel4 = er.sel4; a.cwg = mstride / 8; a.cw = t.cw; a.win_slots = t.win_slots;
   a.xpool = xpool; a.dpool = (uint64_t)(M8 ^ X8);
   a.lens = lens; a.order = w.order; a.n = n;
-  a.R = t.R; a.ntiles = t.ntiles; a.C = t.C; a.nchunks = t.nchunks;
+  a.R = t.R; a.ntiles = t.ntiles; a.nchunks = t.nchunks;
   a.total_work = t.ntiles * t.nchunks; a.work_ctr = w.ctr; a.partial = w.partial;
   a.nstrands = nstrands; a.mp_max = mstride;
   a.cand = cand; a.K = K; a.nfe = cand ? Kc : ix->NF;
-  if (t.NP == 8) s = launch_scan<8>(a, t.grid, t.lds, st);
-  else if (t.NP == 16) s = launch_scan<16>(a, t.grid, t.lds, st);
-  else s = launch_scan<32>(a, t.grid, t.lds, st);
+  a.step = scan_step(ix);
+  a.qsc = t.qs ? er.qsc : nullptr;
+  a.cq = t.cq;
+  if (t.qs && !er.qsc) return fail(MAXSS_ESTATE, "quality mode without position scores");
+  if (t.qs) {
+    if (t.NP == 8) s = launch_scan<8, true>(a, t.grid, t.lds, st);
+    else if (t.NP == 16) s = launch_scan<16, true>(a, t.grid, t.lds, st);
+    else s = launch_scan<32, true>(a, t.grid, t.lds, st);
+  } else {
+    if (t.NP == 8) s = launch_scan<8, false>(a, t.grid, t.lds, st);
+    else if (t.NP == 16) s = launch_scan<16, false>(a, t.grid, t.lds, st);
+    else s = launch_scan<32, false>(a, t.grid, t.lds, st);
+  }
   if (s) return s;
   {
     ProfScope prof("merge", st);
     merge_kernel<<<(n + 255) / 256, 256, 0, st>>>(w.partial, t.nchunks, lens, n, dout);
   }
   if ((s = check_hip(hipGetLastError(), "merge_kernel"))) return s;
-  const size_t rl = (size_t)ix->F + 3 * (size_t)mstride + 16;
+  // genome window + both read orientations (+ their position scores)
+  const size_t rl = (size_t)ix->F + 3 * (size_t)mstride + 16 + (a.qsc ? 4 * (size_t)mstride + 16 : 0);
+  if (rl > 65536 &&
+      (s = check_hip(hipFuncSetAttribute((const void*)rescan_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)rl),
+                     "hipFuncSetAttribute(rescan_kernel)")))
+    return s;
   {
     ProfScope prof("rescan", st);
     rescan_kernel<<<dim3(n, 2), 256, rl, st>>>(ix->codes, ix->F, er.codes, lens, mstride,
-                                               ix->p.match, ix->p.mismatch, nstrands, n, dout);
+                                               ix->p.match, ix->p.mismatch, nstrands,
+                                               scan_step(ix), a.qsc, n, dout);
   }
   return check_hip(hipGetLastError(), "rescan_kernel");
 }
@@ -748,6 +867,8 @@ maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* do
                            const ScanWork& w, const TileOverride* force, hipStream_t st) {
   const uint32_t n = r.n;
   if (n == 0) return MAXSS_OK;
+  if (qual_mode(ix) && !r.qual)
+    return fail(MAXSS_ESTATE, "quality-mode scan of reads without qualities");
   maxss_status s;
   if ((s = encode_reads_into(ix, r, st, w.er))) return s;
   return scan_core(ix, w.er, w.er.lens, n, dout, w, force, nullptr, 0, 0, st);
@@ -779,6 +900,7 @@ extern "C" maxss_status maxss_scan_reads(const maxss_index* index, const maxss_r
   if (!reads->seq || !reads->offsets) return fail(MAXSS_EINVAL, "NULL reads");
   hipStream_t st = (hipStream_t)stream;
   maxss_status s;
+  if ((s = require_quals(ix, reads))) return s;
   if (!reads->on_device && (s = validate_host_reads(ix, reads))) return s;
   int cur = 0;
   if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;

@@ -38,8 +38,8 @@ def test_version(L):
 
 
 def test_struct_sizes():
-    assert ctypes.sizeof(mx.Params) == 24
-    assert ctypes.sizeof(mx.Reads) == 24
+    assert ctypes.sizeof(mx.Params) == 28
+    assert ctypes.sizeof(mx.Reads) == 32
     assert mx.TOP2_DTYPE.itemsize == 32 and mx.ALN_DTYPE.itemsize == 32
 
 
@@ -54,6 +54,9 @@ def test_struct_sizes():
     (dict(max_read_len=9000), "max_read_len"),
     (dict(match=127, max_read_len=1000), "65535"),
     (dict(flags=64), "flags"),
+    (dict(qual_scale=128), "qual_scale"),
+    (dict(mismatch=-4, qual_scale=100), "qual_scale"),
+    (dict(qual_scale=100, max_read_len=1000), "65535"),
 ])
 def test_index_rejects_bad_params(L, kw, msg):
     a = dict(frag_len=64, max_read_len=100, match=1, mismatch=-1, gap=-2, flags=0)

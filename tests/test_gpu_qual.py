@@ -1,0 +1,153 @@
+"""Base-quality scoring on the GPU (position-specific match / mismatch from
+Phred qualities, both phases): records, alignments and CIGARs bit-exact
+against the oracle for every tile shape, host and device reads, the fast
+scan, one strand, the plan and its graph, and the error paths."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_1403_2136_amd as mx
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("frag", "score", "offset", "strand")
+M, X, GAP, QS = 5, -4, -26, 10
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def assert_same(got, ref, what=""):
+    for f in FIELDS:
+        bad = np.nonzero((got[f] != ref[f]).any(axis=1))[0]
+        assert bad.size == 0, "%s: %s differs for %d reads, first %d: gpu %s oracle %s" % (
+            what, f, bad.size, bad[0], got[bad[0]], ref[bad[0]])
+
+
+def _case(seed=7):
+    g = gen.with_n_runs(gen.uniform_genome(21_111, seed), seed + 1, 10, 1, 60)
+    seq = g.seq.copy()
+    seq[15000:15300] = seq[2000:2300]          # exact repeats
+    r = gen.sample_reads(gen.Genome(seq, "q"), 40, seed + 2, [1, 2, 17, 64, 111, 250], 0.0, 0.3,
+                         indel_max=2)
+    q = gen.sample_qualities(r, seed + 3)
+    q[::17] = ord("!")                         # some Q = 0 bases
+    return seq, r, q
+
+
+@pytest.mark.parametrize("F", [4096, 2048, 1024, 48])
+def test_quality_scan_every_tile_shape(F):
+    seq, r, q = _case()
+    ref = oracle.scan(seq, F, r.seq, r.offsets, M, X, nthreads=8, quals=q, qscale=QS)
+    ix = mx.Index(seq, F, 250, M, X, GAP, qual_scale=QS)
+    for np_ in (8, 16, 32):
+        if 128 * np_ > max(F, 1024):
+            continue
+        for R in (8, 32):
+            mx.maxss_index_set_tiles(ix.handle, np_, R, 8)
+            assert_same(ix.scan(r.seq, r.offsets, qual=q), ref, "F=%d NP=%d R=%d" % (F, np_, R))
+    mx.maxss_index_set_tiles(ix.handle, 0, 0, 0)
+    ix.close()
+
+
+def test_quality_device_reads_and_invalid_quality():
+    torch = _torch()
+    seq, r, q = _case(17)
+    q = q.copy()
+    a = int(r.offsets[3])
+    q[a + 1] = ord(" ")                        # read 3: a quality outside '!'..'~'
+    ok = np.ones(r.n, bool)
+    ok[3] = False
+    keep = np.nonzero(ok)[0]
+    sub = r.subset(keep)
+    qs = np.concatenate([q[int(r.offsets[i]):int(r.offsets[i + 1])] for i in keep])
+    ref = oracle.scan(seq, 2048, sub.seq, sub.offsets, M, X, nthreads=8, quals=qs, qscale=QS)
+    ix = mx.Index(seq, 2048, 250, M, X, GAP, qual_scale=QS)
+    s = torch.from_numpy(np.array(r.seq)).cuda()
+    o = torch.from_numpy(r.offsets.astype(np.int64)).cuda()
+    qd = torch.from_numpy(q).cuda()
+    out = torch.zeros(r.n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(s, o, out, qual=qd)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    assert got["frag"][3][0] == mx.MAXSS_READ_INVALID
+    assert_same(got[keep], ref, "device reads")
+    ix.close()
+
+
+def test_quality_fast_and_one_strand():
+    seq, r, q = _case(27)
+    for flags, oflags in [(mx.MAXSS_FAST, oracle.FAST),
+                          (mx.MAXSS_ONE_STRAND, oracle.ONE_STRAND),
+                          (mx.MAXSS_FAST | mx.MAXSS_ONE_STRAND, oracle.FAST | oracle.ONE_STRAND)]:
+        ref = oracle.scan(seq, 2048, r.seq, r.offsets, M, X, flags=oflags, nthreads=8, quals=q,
+                          qscale=QS)
+        ix = mx.Index(seq, 2048, 250, M, X, GAP, flags=flags, qual_scale=QS)
+        assert_same(ix.scan(r.seq, r.offsets, qual=q), ref, "flags %d" % flags)
+        ix.close()
+
+
+@pytest.mark.parametrize("glob", [False, True])
+def test_quality_nw_matches_oracle(glob):
+    seq, r, q = _case(37)
+    flags = mx.MAXSS_NW_GLOBAL if glob else 0
+    ix = mx.Index(seq, 1024, 250, M, X, GAP, flags=flags, qual_scale=QS)
+    top = ix.scan(r.seq, r.offsets, qual=q)
+    ref = oracle.scan(seq, 1024, r.seq, r.offsets, M, X, nthreads=8, quals=q, qscale=QS)
+    assert_same(top, ref, "scan")
+    aln, cig = ix.align(r.seq, r.offsets, top, 60, 2048, qual=q)
+    exp = oracle.align_top(seq, 1024, r.seq, r.offsets, ref, 60, M, X, GAP,
+                           oracle.NW_GLOBAL if glob else oracle.NW_FIT, quals=q, qscale=QS)
+    for i in range(r.n):
+        assert (int(aln["score"][i]), int(aln["strand"][i]), int(aln["ref_begin"][i]),
+                int(aln["ref_end"][i]), cig[i]) == \
+            (exp[i]["score"], exp[i]["strand"], exp[i]["ref_begin"], exp[i]["ref_end"],
+             exp[i]["cigar"]), i
+    ix.close()
+
+
+def test_quality_plan_graph():
+    torch = _torch()
+    seq, r, q = _case(47)
+    ref = oracle.scan(seq, 2048, r.seq, r.offsets, M, X, nthreads=8, quals=q, qscale=QS)
+    ix = mx.Index(seq, 2048, 250, M, X, GAP, qual_scale=QS)
+    plan = mx.Plan(ix, capacity=r.n, pad=50, cigar_stride=512)
+    s = torch.from_numpy(np.array(r.seq)).cuda()
+    o = torch.from_numpy(r.offsets.astype(np.int64)).cuda()
+    qd = torch.from_numpy(q).cuda()
+    top = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    aln = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    cig = torch.zeros(r.n * 512, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            plan.run(s, o, top, aln, cig, stream=stream, graph=True, qual=qd)
+        stream.synchronize()
+        assert_same(top.cpu().numpy().view(mx.TOP2_DTYPE), ref, "graph replay %d" % rep)
+    exp = oracle.align_top(seq, 2048, r.seq, r.offsets, ref, 50, M, X, GAP, quals=q, qscale=QS)
+    a = aln.cpu().numpy().view(mx.ALN_DTYPE)
+    assert [int(x) for x in a["score"]] == [e["score"] for e in exp]
+    plan.close()
+    ix.close()
+
+
+def test_quality_index_needs_qualities():
+    seq, r, q = _case(57)
+    ix = mx.Index(seq, 2048, 250, M, X, GAP, qual_scale=QS)
+    with pytest.raises(mx.MaxssError) as e:
+        ix.scan(r.seq, r.offsets)
+    assert e.value.status == mx.MAXSS_EINVAL
+    bad = q.copy()
+    bad[5] = 0x7F
+    with pytest.raises(mx.MaxssError) as e:
+        ix.scan(r.seq, r.offsets, qual=bad)
+    assert e.value.status == mx.MAXSS_EINVAL
+    ix.close()
+    # plain indexes ignore qualities
+    ix = mx.Index(seq, 2048, 250, M, X, GAP)
+    assert_same(ix.scan(r.seq, r.offsets, qual=q),
+                oracle.scan(seq, 2048, r.seq, r.offsets, M, X, nthreads=8), "plain")
+    ix.close()
