@@ -26,7 +26,8 @@
  *   - Bases are ASCII A, C, G, T, N in either case.  N (in the genome, in a
  *     read, or the padding past the genome end) scores `mismatch` against
  *     everything, including N.
- *   - All scores are exact integers.
+ *   - All scores are exact integers (with base qualities: integers in units of
+ *     1/qual_scale, see maxss_params).
  */
 #ifndef MAXSS_H
 #define MAXSS_H
@@ -165,8 +166,11 @@ maxss_status maxss_index_info(const maxss_index* index, uint64_t* genome_len,
  * f*F + o may run into the next fragment and past the genome end -- reduced to
  * the best and second-best fragments (one maxss_top2 per read, in read
  * order).  Reads of any lengths may be mixed in one call.
- * out: n records, host or device memory as the reads.
- * Errors: EINVAL (NULL pointers, n = 0 is allowed and does nothing), ETOOLONG
+ * out: n records, host or device memory as the reads.  With MAXSS_FAST the
+ * windows score every other read base; with qual_scale > 0 they score with the
+ * reads' position-specific scores (reads->qual required).
+ * Errors: EINVAL (NULL pointers, n = 0 is allowed and does nothing, qualities
+ * missing on a quality-mode index, a host quality outside '!'..'~'), ETOOLONG
  * (host reads only: a read of length 0 or > max_read_len), ENOMEM, EDEVICE. */
 maxss_status maxss_scan_reads(const maxss_index* index, const maxss_reads* reads,
                               maxss_top2* out, void* stream);
@@ -183,8 +187,11 @@ maxss_status maxss_scan_reads(const maxss_index* index, const maxss_reads* reads
  * top: n records from maxss_scan_reads; out: n records; cigar: n *
  * cigar_stride bytes, read i's NUL-terminated CIGAR at cigar + i*cigar_stride
  * (cigar_stride >= 2; a CIGAR that does not fit is truncated and flagged).
- * Pointers are host or device memory as the reads.  Errors: EINVAL, ETOOLONG
- * (host reads), ENOMEM, EDEVICE. */
+ * With qual_scale > 0 each DP row scores with its read base's position-specific
+ * pair (reversed qualities for strand 1) and the gap is gap * qual_scale.
+ * Pointers are host or device memory as the reads.  Errors: EINVAL (also:
+ * qualities missing on a quality-mode index), ETOOLONG (host reads), ENOMEM,
+ * EDEVICE. */
 maxss_status maxss_align_top(const maxss_index* index, const maxss_reads* reads,
                              const maxss_top2* top, uint32_t pad, maxss_aln* out,
                              char* cigar, uint64_t cigar_stride, void* stream);
