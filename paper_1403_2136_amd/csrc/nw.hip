@@ -15,6 +15,8 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace maxss {
@@ -242,9 +244,266 @@ __global__ __launch_bounds__(kNwThreads) void nw_kernel(NwArgs a) {
   }
 }
 
+// The same DP with one wave per read (persistent over reads, 64 threads per
+// workgroup, no barrier inside a row).  Lane l owns region columns
+// [1 + l*CW, 1 + (l+1)*CW): their previous-row values and genome codes live in
+// registers, the left neighbour's last value comes by a lane shuffle, and the
+// max-plus prefix across lanes is a 64-lane shuffle scan.  Moves go to the
+// slab in the block kernel's layout (column j's two bits at byte (j-1)/4 of
+// the row), and lane 0 traces back as there.  Values are int32: the host uses
+// this kernel only when every DP value provably fits.
+template <int CW>
+__global__ __launch_bounds__(64) void nw_wave_kernel(NwArgs a) {
+  extern __shared__ uint8_t shw[];
+  uint8_t* lq = shw;                                        // m_max read codes
+  char* ops = (char*)(shw + ((a.m_max + 15u) & ~15u));     // m_max + 64*CW ops
+  const int lane = (int)threadIdx.x;
+  uint8_t* slab = a.slab + (uint64_t)blockIdx.x * a.m_max * a.rowbytes;
+  const int g = -a.gap;  // >= 0
+  for (uint32_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    const uint32_t m = a.lens[i];
+    const int f = a.top[i].frag[0];
+    maxss_aln* o = a.out + i;
+    char* cg = a.cigar + (uint64_t)i * a.cigar_stride;
+    const int strand = a.top[i].strand[0];
+    if (m == 0 || f < 0 || (uint32_t)f >= a.NF || (strand != 0 && strand != 1)) {
+      if (lane == 0) {
+        o->score = 0; o->strand = -1; o->flags = MAXSS_ALN_SKIPPED;
+        o->_pad[0] = o->_pad[1] = 0;
+        o->ref_begin = o->ref_end = -1; o->cigar_len = 0; o->_pad2 = 0;
+        cg[0] = 0;
+      }
+      continue;
+    }
+    const long long start = (long long)f * a.F;
+    long long ra = start - (long long)a.pad;
+    if (ra < 0) ra = 0;
+    long long rb = start + (long long)a.F + (long long)m - 1 + (long long)a.pad;
+    if (rb > (long long)a.G) rb = (long long)a.G;
+    const int ncols = (int)(rb - ra);
+    __syncthreads();  // the previous read's traceback is done with LDS
+    const uint8_t* rc = a.rcodes + (uint64_t)i * a.mstride;
+    for (uint32_t k = lane; k < m; k += 64) {
+      uint8_t c = strand ? rc[m - 1 - k] : rc[k];
+      if (strand) c = c == kN ? kN : (uint8_t)(3 - c);
+      lq[k] = c;
+    }
+    const int j0 = 1 + lane * CW;
+    uint32_t gv[CW / 4];
+#pragma unroll
+    for (int w = 0; w < CW / 4; w++) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int j = j0 + 4 * w + b;
+        const uint32_t c = j <= ncols ? a.gcodes[ra + j - 1] : (uint32_t)kN;
+        v |= c << (8 * b);
+      }
+      gv[w] = v;
+    }
+    int prev[CW];
+#pragma unroll
+    for (int t = 0; t < CW; t++) prev[t] = a.global_mode ? (j0 + t) * a.gap : 0;
+    __syncthreads();  // lq written
+    for (uint32_t r = 1; r <= m; r++) {
+      const uint32_t q = lq[r - 1];
+      int Mr = a.M, Xr = a.X;
+      if (a.qsc) {
+        const uint16_t v = a.qsc[(uint64_t)i * a.mstride + (strand ? m - r : r - 1)];
+        Mr = (int)(int8_t)(v & 0xFFu);
+        Xr = (int)(int8_t)(v >> 8);
+      }
+      // Row-invariant per-column values (unpacked genome codes, j*g) are
+      // recomputed every row instead of being held in registers across rows:
+      // the copies below look row-dependent to the compiler.
+      int gg = g;
+      asm volatile("" : "+s"(gg));
+      uint32_t gw[CW / 4];
+#pragma unroll
+      for (int w = 0; w < CW / 4; w++) {
+        gw[w] = gv[w];
+        asm volatile("" : "+v"(gw[w]));
+      }
+      // D[r-1][j0-1]: the left lane's last column, or column 0
+      int pl = __shfl_up(prev[CW - 1], 1, 64);
+      if (lane == 0) pl = (int)(r - 1) * a.gap;
+      // pass 1: T[j] = max(diag, up) replaces the previous row in place, with
+      // one bit per column for "diagonal wins the tie", and this lane's
+      // running max of T[j] + j*g
+      int run = INT_MIN, old = pl;
+      uint32_t dwin[(CW + 31) / 32];
+#pragma unroll
+      for (int w = 0; w < (CW + 31) / 32; w++) dwin[w] = 0;
+#pragma unroll
+      for (int t = 0; t < CW; t++) {
+        const uint32_t gc = (gw[t >> 2] >> (8 * (t & 3))) & 0xFFu;
+        const int d = old + ((q == gc && q != kN) ? Mr : Xr);
+        const int u = prev[t] + a.gap;
+        old = prev[t];
+        prev[t] = max(d, u);
+        dwin[t >> 5] |= (d >= u ? 1u : 0u) << (t & 31);
+        run = max(run, prev[t] + (j0 + t) * gg);
+      }
+      // exclusive max-scan across lanes; column 0 (D[r][0] = r*gap) seeds it
+      int x = run;
+#pragma unroll
+      for (int of = 1; of < 64; of <<= 1) {
+        const int y = __shfl_up(x, of, 64);
+        if (lane >= of) x = max(x, y);
+      }
+      int carry = __shfl_up(x, 1, 64);
+      if (lane == 0) carry = INT_MIN;
+      carry = max(carry, (int)r * a.gap);
+      // pass 2: D = max(T, left chain); the move is diagonal, then up, then
+      // left on ties: T's own winner when D == T, else left
+      uint8_t* mrow = slab + (uint64_t)(r - 1) * a.rowbytes + lane * (CW / 4);
+      uint32_t packed = 0;
+#pragma unroll
+      for (int t = 0; t < CW; t++) {
+        const int jg = (j0 + t) * gg;
+        const int T = prev[t];
+        carry = max(carry, T + jg);
+        const int D = carry - jg;
+        const uint32_t mv = (D == T) ? (((dwin[t >> 5] >> (t & 31)) & 1u) ? 0u : 1u) : 2u;
+        prev[t] = D;
+        packed |= mv << (2 * (t & 3));
+        if ((t & 3) == 3) {
+          mrow[t >> 2] = (uint8_t)packed;
+          packed = 0;
+        }
+      }
+    }
+    // end column: the whole region (global) or the best, smallest column
+    int bestv, bestj;
+    if (a.global_mode) {
+      const int owner = (ncols - 1) / CW, tt = (ncols - 1) - owner * CW;
+      int v = 0;
+#pragma unroll
+      for (int t = 0; t < CW; t++)
+        if (t == tt) v = prev[t];
+      bestv = __shfl(v, owner, 64);
+      bestj = ncols;
+    } else {
+      int bv = INT_MIN, bj = INT_MAX;
+      if (lane == 0) { bv = (int)m * a.gap; bj = 0; }
+#pragma unroll
+      for (int t = 0; t < CW; t++)
+        if (j0 + t <= ncols && prev[t] > bv) { bv = prev[t]; bj = j0 + t; }
+#pragma unroll
+      for (int of = 32; of > 0; of >>= 1) {
+        const int v2 = __shfl_xor(bv, of, 64), j2 = __shfl_xor(bj, of, 64);
+        if (v2 > bv || (v2 == bv && j2 < bj)) { bv = v2; bj = j2; }
+      }
+      bestv = bv;
+      bestj = bj;
+    }
+    __threadfence_block();  // every lane's moves are visible to lane 0
+    if (lane == 0) {
+      uint32_t len = 0;
+      int ii = (int)m, jj = bestj;
+      while (ii > 0 || (a.global_mode && jj > 0)) {
+        uint32_t mv;
+        if (ii == 0) mv = 2;
+        else if (jj == 0) mv = 1;
+        else {
+          const uint32_t t = (uint32_t)(jj - 1);
+          const uint8_t byte = slab[(uint64_t)(ii - 1) * a.rowbytes + (t >> 2)];
+          mv = (byte >> (2 * (t & 3))) & 3u;
+        }
+        if (mv == 0) {
+          const uint8_t qc = lq[ii - 1], gc = a.gcodes[ra + jj - 1];
+          ops[len++] = (qc == gc && qc != kN) ? '=' : 'X';
+          ii--; jj--;
+        } else if (mv == 1) {
+          ops[len++] = 'I';
+          ii--;
+        } else {
+          ops[len++] = 'D';
+          jj--;
+        }
+      }
+      uint64_t w = 0;
+      bool trunc = false;
+      for (int p = (int)len - 1; p >= 0;) {
+        const char op = ops[p];
+        int q2 = p;
+        while (q2 >= 0 && ops[q2] == op) q2--;
+        uint32_t run2 = (uint32_t)(p - q2);
+        char dig[12];
+        int nd = 0;
+        do { dig[nd++] = (char)('0' + run2 % 10); run2 /= 10; } while (run2);
+        if (w + (uint64_t)nd + 1 + 1 > a.cigar_stride) { trunc = true; break; }
+        while (nd) cg[w++] = dig[--nd];
+        cg[w++] = op;
+        p = q2;
+      }
+      cg[w] = 0;
+      o->score = bestv;
+      o->strand = (int8_t)strand;
+      o->flags = trunc ? MAXSS_ALN_TRUNCATED : 0;
+      o->_pad[0] = o->_pad[1] = 0;
+      o->ref_begin = ra + jj;
+      o->ref_end = ra + bestj;
+      o->cigar_len = (uint32_t)w;
+      o->_pad2 = 0;
+    }
+  }
+}
+
+// Columns per lane of the wave kernel's instantiations.
+static constexpr int kWaveCw[] = {8, 16, 24, 32, 40, 48, 56, 64, 72, 80, 88, 96};
+
+template <int CW>
+static const void* wave_fn() {
+  return (const void*)nw_wave_kernel<CW>;
+}
+
+static const void* wave_kernel_for(int cw) {
+  switch (cw) {
+    case 8: return wave_fn<8>();
+    case 16: return wave_fn<16>();
+    case 24: return wave_fn<24>();
+    case 32: return wave_fn<32>();
+    case 40: return wave_fn<40>();
+    case 48: return wave_fn<48>();
+    case 56: return wave_fn<56>();
+    case 64: return wave_fn<64>();
+    case 72: return wave_fn<72>();
+    case 80: return wave_fn<80>();
+    case 88: return wave_fn<88>();
+    default: return wave_fn<96>();
+  }
+}
+
 maxss_status nw_shape(const Index* ix, uint32_t n, uint32_t pad, NwShape* sh) {
   const uint32_t m_max = ix->p.max_read_len;
   const uint64_t ncols_need = (uint64_t)ix->F + m_max - 1 + 2ull * pad;
+  // the wave kernel: 64 lanes of up to 96 columns, and every DP value (cell
+  // scores and gaps along at most m_max + ncols moves, plus the j*g offset of
+  // the prefix) within int32
+  const int64_t qs = ix->p.qual_scale > 0 ? ix->p.qual_scale : 1;
+  const int64_t step_max = std::max<int64_t>({(int64_t)ix->p.match * qs, -(int64_t)ix->p.mismatch * qs,
+                                              -(int64_t)ix->p.gap * qs, 1});
+  const uint64_t cw64 = (ncols_need + 63) / 64;
+  sh->wave_cw = 0;
+  if (cw64 <= 96 && (int64_t)(m_max + 2 * ncols_need + 64) * step_max < (1ll << 30)) {
+    for (int c : kWaveCw)
+      if ((uint64_t)c >= cw64) { sh->wave_cw = (uint32_t)c; break; }
+  }
+  if (sh->wave_cw) {
+    sh->cw = sh->wave_cw;
+    sh->ncols_max = 64 * sh->wave_cw;
+    sh->rowbytes = sh->ncols_max / 4;
+    sh->lds = ((m_max + 15u) & ~15u) + m_max + sh->ncols_max + 16;
+    const void* fn = wave_kernel_for((int)sh->wave_cw);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64, sh->lds) != hipSuccess || occ < 1)
+      occ = 1;
+    uint32_t grid = (uint32_t)ix->num_cu * (uint32_t)occ;
+    if (n && grid > n) grid = n;
+    sh->grid = grid ? grid : 1;
+    return MAXSS_OK;
+  }
   uint32_t cw = (uint32_t)((ncols_need + kNwThreads - 1) / kNwThreads);
   cw = (cw + 3) & ~3u;
   sh->cw = cw;
@@ -290,7 +549,21 @@ maxss_status nw_pipeline(const Index* ix, const EncodedReads& er, uint32_t n,
   const uint32_t grid = sh.grid < n ? sh.grid : n;
   {
     ProfScope prof("nw", st);
-    nw_kernel<<<grid, kNwThreads, sh.lds, st>>>(a);
+    switch (sh.wave_cw) {
+      case 0: nw_kernel<<<grid, kNwThreads, sh.lds, st>>>(a); break;
+      case 8: nw_wave_kernel<8><<<grid, 64, sh.lds, st>>>(a); break;
+      case 16: nw_wave_kernel<16><<<grid, 64, sh.lds, st>>>(a); break;
+      case 24: nw_wave_kernel<24><<<grid, 64, sh.lds, st>>>(a); break;
+      case 32: nw_wave_kernel<32><<<grid, 64, sh.lds, st>>>(a); break;
+      case 40: nw_wave_kernel<40><<<grid, 64, sh.lds, st>>>(a); break;
+      case 48: nw_wave_kernel<48><<<grid, 64, sh.lds, st>>>(a); break;
+      case 56: nw_wave_kernel<56><<<grid, 64, sh.lds, st>>>(a); break;
+      case 64: nw_wave_kernel<64><<<grid, 64, sh.lds, st>>>(a); break;
+      case 72: nw_wave_kernel<72><<<grid, 64, sh.lds, st>>>(a); break;
+      case 80: nw_wave_kernel<80><<<grid, 64, sh.lds, st>>>(a); break;
+      case 88: nw_wave_kernel<88><<<grid, 64, sh.lds, st>>>(a); break;
+      default: nw_wave_kernel<96><<<grid, 64, sh.lds, st>>>(a); break;
+    }
   }
   return check_hip(hipGetLastError(), "nw_kernel");
 }

@@ -527,11 +527,13 @@ __global__ void merge_kernel(const int4* __restrict__ partial, uint32_t nchunks,
 // Exact re-scan of one winning fragment of one read (int32, one offset per
 // thread and strand) to find its representative window: the smallest strand,
 // then the smallest offset, among the windows reaching the fragment's value.
-// With step 2 only read positions 0, 2, 4, ... of each strand are scored.
+// With STEP 2 only read positions 0, 2, 4, ... of each strand are scored;
+// QS scores with the reads' position-specific pairs.
+template <uint32_t STEP, bool QS>
 __global__ __launch_bounds__(256) void rescan_kernel(
     const uint8_t* __restrict__ gcodes, uint32_t F, const uint8_t* __restrict__ rcodes,
     const uint32_t* __restrict__ lens, uint32_t mstride, int M, int X, uint32_t nstrands,
-    uint32_t step, const uint16_t* __restrict__ qsc, uint32_t n, maxss_top2* __restrict__ out) {
+    const uint16_t* __restrict__ qsc, uint32_t n, maxss_top2* __restrict__ out) {
   extern __shared__ uint8_t sh[];
   const uint32_t i = blockIdx.x, which = blockIdx.y;
   const uint32_t m = lens[i];
@@ -548,7 +550,7 @@ __global__ __launch_bounds__(256) void rescan_kernel(
     uint8_t c = rc[k];
     lq[k] = c;
     lq[m + (m - 1 - k)] = c == kN ? kN : (uint8_t)(3 - c);
-    if (qsc) {
+    if constexpr (QS) {
       const uint16_t v = qsc[(uint64_t)i * mstride + k];
       lp[k] = v;
       lp[m + (m - 1 - k)] = v;
@@ -560,9 +562,9 @@ __global__ __launch_bounds__(256) void rescan_kernel(
     const uint8_t* q = lq + s * m;
     for (uint32_t o = threadIdx.x; o < F; o += blockDim.x) {
       int H = 0, B = 0;
-      for (uint32_t k = 0; k < m; k += step) {
+      for (uint32_t k = 0; k < m; k += STEP) {
         const uint8_t g = lg[o + k], c = q[k];
-        if (qsc) {
+        if constexpr (QS) {
           const uint16_t v = lp[s * m + k];
           H += (g == c && c != kN) ? (int)(int8_t)(v & 0xFFu) : (int)(int8_t)(v >> 8);
         } else {
@@ -849,16 +851,32 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   if ((s = check_hip(hipGetLastError(), "merge_kernel"))) return s;
   // genome window + both read orientations (+ their position scores)
   const size_t rl = (size_t)ix->F + 3 * (size_t)mstride + 16 + (a.qsc ? 4 * (size_t)mstride + 16 : 0);
+  const bool fast = scan_step(ix) == 2, qs = a.qsc != nullptr;
+  const void* fn = fast ? (qs ? (const void*)rescan_kernel<2, true> : (const void*)rescan_kernel<2, false>)
+                        : (qs ? (const void*)rescan_kernel<1, true> : (const void*)rescan_kernel<1, false>);
   if (rl > 65536 &&
-      (s = check_hip(hipFuncSetAttribute((const void*)rescan_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)rl),
+      (s = check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rl),
                      "hipFuncSetAttribute(rescan_kernel)")))
     return s;
   {
     ProfScope prof("rescan", st);
-    rescan_kernel<<<dim3(n, 2), 256, rl, st>>>(ix->codes, ix->F, er.codes, lens, mstride,
-                                               ix->p.match, ix->p.mismatch, nstrands,
-                                               scan_step(ix), a.qsc, n, dout);
+    const dim3 g(n, 2);
+    if (fast && qs)
+      rescan_kernel<2, true><<<g, 256, rl, st>>>(ix->codes, ix->F, er.codes, lens, mstride,
+                                                 ix->p.match, ix->p.mismatch, nstrands, a.qsc, n,
+                                                 dout);
+    else if (fast)
+      rescan_kernel<2, false><<<g, 256, rl, st>>>(ix->codes, ix->F, er.codes, lens, mstride,
+                                                  ix->p.match, ix->p.mismatch, nstrands, a.qsc, n,
+                                                  dout);
+    else if (qs)
+      rescan_kernel<1, true><<<g, 256, rl, st>>>(ix->codes, ix->F, er.codes, lens, mstride,
+                                                 ix->p.match, ix->p.mismatch, nstrands, a.qsc, n,
+                                                 dout);
+    else
+      rescan_kernel<1, false><<<g, 256, rl, st>>>(ix->codes, ix->F, er.codes, lens, mstride,
+                                                  ix->p.match, ix->p.mismatch, nstrands, a.qsc, n,
+                                                  dout);
   }
   return check_hip(hipGetLastError(), "rescan_kernel");
 }
