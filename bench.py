@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 CU, SIMD_LANES, CLOCK = 256, 64, 2.4e9          # 256 CUs x 4 SIMD16 = 64 lanes/clk/CU
 INT16_PACKED_OPS = CU * SIMD_LANES * CLOCK * 2   # 16-bit lane ops/s with packed math
-OPS_PER_CELL = 3   # substitution-score select, saturating add (Kadane's add+clamp), running max
+# 16-bit lane ops per cell of the scan's inner loop on these workloads (score
+# bound <= 31744): score select and saturating add (Kadane's add + clamp) every
+# step, one three-way running max per two steps
+OPS_PER_CELL = 2.5
 
 
 def recorded_traffic(workload: str):

@@ -23,8 +23,11 @@
 //   * Kadane runs on packed int16 with a -32768 bias: with H' = H - 32768,
 //     max(0, H + sigma) is exactly the signed-saturating add H' + sigma
 //     (v_pk_add_i16 with clamp) as long as H + sigma stays below 65536, which
-//     max_read_len * match <= 65535 guarantees.  B' = max(B', H') is one
-//     v_pk_max_i16.  So each pair of cells costs three VALU instructions.
+//     max_read_len * match <= 65535 guarantees.  When the bound is at most
+//     31744, two steps share one v_pk_minimum3_f16 for B' = max(B', H'_t,
+//     H'_t+1) (the biased values read as binary16 fall as h grows), so each
+//     pair of cells costs five VALU instructions per two steps; above it,
+//     B' = max(B', H') is one v_pk_max_i16 per step (three per step).
 //   * The window of selector words a lane needs slides by one per step; it is
 //     kept in registers (2*NP words) and refilled from LDS every NP steps.
 //   * A persistent grid pulls (read tile x fragment chunk) work items from an
@@ -143,6 +146,44 @@ __device__ inline uint64_t step_pool(uint32_t c, uint32_t pair, uint64_t xpool, 
   }
 }
 
+// One Kadane step of one offset pair: v_perm_b32 for the two scores,
+// v_pk_add_i16 with clamp for H, v_pk_max_i16 for B.
+__device__ inline void kadane_one(s16x2& H, s16x2& B, uint32_t w, uint32_t lo, uint32_t hi) {
+  H = __builtin_elementwise_add_sat(H, __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(hi, lo, w)));
+  B = __builtin_elementwise_max(B, H);
+}
+
+// Two Kadane steps of two offset pairs (interleaved, so that no add reads
+// the result of the instruction right before it).  The biased values
+// h - 32768 (h in [0, 31744]) read as binary16 are -0 and negative numbers
+// that decrease strictly as h grows (subnormals included, which the kernels
+// keep), so the IEEE minimum of three such values is the largest h:
+// B' = max(B', H'_t, H'_t+1) is one v_pk_minimum3_f16, five VALU
+// instructions per pair and two steps.
+__device__ inline void kadane_two(s16x2& Ha, s16x2& Ba, uint32_t wa0, uint32_t wa1, s16x2& Hb,
+                                  s16x2& Bb, uint32_t wb0, uint32_t wb1, uint32_t lo0,
+                                  uint32_t hi0, uint32_t lo1, uint32_t hi1) {
+  typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+  const s16x2 sa0 = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(hi0, lo0, wa0));
+  const s16x2 sb0 = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(hi0, lo0, wb0));
+  const s16x2 ha = __builtin_elementwise_add_sat(Ha, sa0);
+  const s16x2 hb = __builtin_elementwise_add_sat(Hb, sb0);
+  const s16x2 sa1 = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(hi1, lo1, wa1));
+  const s16x2 sb1 = __builtin_bit_cast(s16x2, __builtin_amdgcn_perm(hi1, lo1, wb1));
+  Ha = __builtin_elementwise_add_sat(ha, sa1);
+  Hb = __builtin_elementwise_add_sat(hb, sb1);
+  Ba = __builtin_bit_cast(
+      s16x2, __builtin_elementwise_minimum(
+                 __builtin_elementwise_minimum(__builtin_bit_cast(f16x2, Ba),
+                                               __builtin_bit_cast(f16x2, ha)),
+                 __builtin_bit_cast(f16x2, Ha)));
+  Bb = __builtin_bit_cast(
+      s16x2, __builtin_elementwise_minimum(
+                 __builtin_elementwise_minimum(__builtin_bit_cast(f16x2, Bb),
+                                               __builtin_bit_cast(f16x2, hb)),
+                 __builtin_bit_cast(f16x2, Hb)));
+}
+
 // Pair of scan position t of a block whose pairs were read into qw (two
 // positions per word, the block starting at an even position).
 __device__ inline uint32_t pair_at(const uint32_t* qw, int t) {
@@ -150,8 +191,10 @@ __device__ inline uint32_t pair_at(const uint32_t* qw, int t) {
 }
 
 // SUB Kadane steps (SUB <= 8) at read positions [k, k+SUB) (k even), with the
-// window loaded from LDS for exactly these steps.
-template <int NP, int SUB, bool QS>
+// window loaded from LDS for exactly these steps.  WIDE (scores may pass
+// 31744): B' = max(B', H') after every step; otherwise two steps at a time
+// with one packed minimum3 for B (kadane_two).
+template <int NP, int SUB, bool QS, bool WIDE>
 __device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lbase,
                                   const uint32_t* __restrict__ lc,
                                   const uint32_t* __restrict__ lq, uint32_t k, uint64_t xpool,
@@ -164,18 +207,24 @@ __device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lba
 #pragma unroll
   for (int i = 0; i < (SUB + 1) / 2; i++)
     qw[i] = QS ? __builtin_amdgcn_readfirstlane(lq[k / 2 + i]) : 0u;
+  constexpr int PAIRED = WIDE ? 0 : SUB & ~1;
 #pragma unroll
-  for (int t = 0; t < SUB; t++) {
-    const uint32_t c = (cc >> (4 * t)) & 15u;
-    const uint64_t pool = step_pool<QS>(c, pair_at(qw, t), xpool, dpool);
-    const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
+  for (int t = 0; t < PAIRED; t += 2) {
+    const uint64_t p0 = step_pool<QS>((cc >> (4 * t)) & 15u, pair_at(qw, t), xpool, dpool);
+    const uint64_t p1 =
+        step_pool<QS>((cc >> (4 * t + 4)) & 15u, pair_at(qw, t + 1), xpool, dpool);
 #pragma unroll
-    for (int j = 0; j < NP; j++) {
-      uint32_t sg = __builtin_amdgcn_perm(phi, plo, win[j + t]);
-      H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
-    }
+    for (int j = 0; j < NP; j += 2)
+      kadane_two(H[j], B[j], win[j + t], win[j + t + 1], H[j + 1], B[j + 1], win[j + t + 1],
+                 win[j + t + 2], (uint32_t)p0, (uint32_t)(p0 >> 32), (uint32_t)p1,
+                 (uint32_t)(p1 >> 32));
+  }
 #pragma unroll
-    for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
+  for (int t = PAIRED; t < SUB; t++) {
+    const uint64_t pool = step_pool<QS>((cc >> (4 * t)) & 15u, pair_at(qw, t), xpool, dpool);
+#pragma unroll
+    for (int j = 0; j < NP; j++)
+      kadane_one(H[j], B[j], win[j + t], (uint32_t)pool, (uint32_t)(pool >> 32));
   }
 }
 
@@ -183,7 +232,7 @@ __device__ inline void kadane_sub(const uint32_t* __restrict__ lds, uint32_t lba
 // kb..kb+NP-1 of the lane) and second[0..NP) (words kb+NP..kb+2NP-1).
 // first[t] is last read at step t, so right after step t it is reloaded with
 // word kb+2NP+t: the block after next finds it there as its `second` half.
-template <int NP, bool QS>
+template <int NP, bool QS, bool WIDE>
 __device__ inline void kadane_block(uint32_t (&first)[NP], const uint32_t (&second)[NP],
                                     const uint32_t* __restrict__ lw, const uint32_t (&cc)[NP / 8],
                                     const uint32_t* __restrict__ lqb, uint64_t xpool,
@@ -191,20 +240,35 @@ __device__ inline void kadane_block(uint32_t (&first)[NP], const uint32_t (&seco
   uint32_t qw[NP / 2];
 #pragma unroll
   for (int i = 0; i < NP / 2; i++) qw[i] = QS ? __builtin_amdgcn_readfirstlane(lqb[i]) : 0u;
+  if constexpr (WIDE) {
 #pragma unroll
-  for (int t = 0; t < NP; t++) {
-    const uint32_t c = (cc[t >> 3] >> (4 * (t & 7))) & 15u;
-    const uint64_t pool = step_pool<QS>(c, pair_at(qw, t), xpool, dpool);
-    const uint32_t plo = (uint32_t)pool, phi = (uint32_t)(pool >> 32);
+    for (int t = 0; t < NP; t++) {
+      const uint64_t pool =
+          step_pool<QS>((cc[t >> 3] >> (4 * (t & 7))) & 15u, pair_at(qw, t), xpool, dpool);
 #pragma unroll
-    for (int j = 0; j < NP; j++) {
-      const uint32_t w = (j + t < NP) ? first[j + t] : second[j + t - NP];
-      uint32_t sg = __builtin_amdgcn_perm(phi, plo, w);
-      H[j] = __builtin_elementwise_add_sat(H[j], __builtin_bit_cast(s16x2, sg));
+      for (int j = 0; j < NP; j++)
+        kadane_one(H[j], B[j], (j + t < NP) ? first[j + t] : second[j + t - NP], (uint32_t)pool,
+                   (uint32_t)(pool >> 32));
+      first[t] = lw[t];
     }
+  } else {
 #pragma unroll
-    for (int j = 0; j < NP; j++) B[j] = __builtin_elementwise_max(B[j], H[j]);
-    first[t] = lw[t];
+    for (int t = 0; t < NP; t += 2) {
+      const uint64_t p0 =
+          step_pool<QS>((cc[t >> 3] >> (4 * (t & 7))) & 15u, pair_at(qw, t), xpool, dpool);
+      const uint64_t p1 = step_pool<QS>((cc[(t + 1) >> 3] >> (4 * ((t + 1) & 7))) & 15u,
+                                        pair_at(qw, t + 1), xpool, dpool);
+#pragma unroll
+      for (int j = 0; j < NP; j += 2) {
+        const uint32_t w0 = (j + t < NP) ? first[j + t] : second[j + t - NP];
+        const uint32_t w1 = (j + t + 1 < NP) ? first[j + t + 1] : second[j + t + 1 - NP];
+        const uint32_t w2 = (j + t + 2 < NP) ? first[j + t + 2] : second[j + t + 2 - NP];
+        kadane_two(H[j], B[j], w0, w1, H[j + 1], B[j + 1], w1, w2, (uint32_t)p0,
+                   (uint32_t)(p0 >> 32), (uint32_t)p1, (uint32_t)(p1 >> 32));
+      }
+      first[t] = lw[t];  // words t and t+1 are last read by the steps above
+      first[t + 1] = lw[t + 1];
+    }
   }
 }
 
@@ -213,7 +277,7 @@ __device__ inline void kadane_block(uint32_t (&first)[NP], const uint32_t (&seco
 // two register halves that swap roles every block), then the last m % NP
 // steps as unrolled sub-blocks of 8/4/2/1 steps, so no padding step is
 // computed.  Returns the lane's per-pair maxima (biased by -32768) in B.
-template <int NP, bool QS>
+template <int NP, bool QS, bool WIDE>
 __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t lane,
                                     const uint32_t* __restrict__ lc,
                                     const uint32_t* __restrict__ lq, uint32_t m,
@@ -248,38 +312,38 @@ __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t l
       for (int i = 0; i < CW; i++) cc[i] = cn[i];
 #pragma unroll
       for (int i = 0; i < CW; i++) cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + NP) / 8 + i]);
-      kadane_block<NP, QS>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, lq + kb / 2, xpool,
+      kadane_block<NP, QS, WIDE>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, lq + kb / 2, xpool,
                            dpool, H, B);
 #pragma unroll
       for (int i = 0; i < CW; i++) cc[i] = cn[i];
 #pragma unroll
       for (int i = 0; i < CW; i++)
         cn[i] = __builtin_amdgcn_readfirstlane(lc[(kb + 2 * NP) / 8 + i]);
-      kadane_block<NP, QS>(wB, wA, lds + lbase + pb + 3 * (NP + 1), cc, lq + (kb + NP) / 2,
+      kadane_block<NP, QS, WIDE>(wB, wA, lds + lbase + pb + 3 * (NP + 1), cc, lq + (kb + NP) / 2,
                            xpool, dpool, H, B);
     }
     if (kb < mfull) {  // one block left
       uint32_t cc[CW];
 #pragma unroll
       for (int i = 0; i < CW; i++) cc[i] = cn[i];
-      kadane_block<NP, QS>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, lq + kb / 2, xpool,
+      kadane_block<NP, QS, WIDE>(wA, wB, lds + lbase + pb + 2 * (NP + 1), cc, lq + kb / 2, xpool,
                            dpool, H, B);
     }
   }
   const uint32_t rem = m - mfull;
   uint32_t k = mfull;
   if (NP > 16 && (rem & 16)) {
-    kadane_sub<NP, 8, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
-    kadane_sub<NP, 8, QS>(lds, lbase, lc, lq, k + 8, xpool, dpool, H, B);
+    kadane_sub<NP, 8, QS, WIDE>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
+    kadane_sub<NP, 8, QS, WIDE>(lds, lbase, lc, lq, k + 8, xpool, dpool, H, B);
     k += 16;
   }
   if (NP > 8 && (rem & 8)) {
-    kadane_sub<NP, 8, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
+    kadane_sub<NP, 8, QS, WIDE>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
     k += 8;
   }
-  if (rem & 4) { kadane_sub<NP, 4, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B); k += 4; }
-  if (rem & 2) { kadane_sub<NP, 2, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B); k += 2; }
-  if (rem & 1) kadane_sub<NP, 1, QS>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
+  if (rem & 4) { kadane_sub<NP, 4, QS, WIDE>(lds, lbase, lc, lq, k, xpool, dpool, H, B); k += 4; }
+  if (rem & 2) { kadane_sub<NP, 2, QS, WIDE>(lds, lbase, lc, lq, k, xpool, dpool, H, B); k += 2; }
+  if (rem & 1) kadane_sub<NP, 1, QS, WIDE>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
 }
 
 __device__ inline int wave_max_i32(int v) {
@@ -288,7 +352,7 @@ __device__ inline int wave_max_i32(int v) {
   return v;
 }
 
-template <int NP, bool QS>
+template <int NP, bool QS, bool WIDE>
 __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t HALF = 64u * NP, S = 128u * NP;
@@ -376,7 +440,7 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
           uint32_t bm = 0x80008000u;
           for (uint32_t s = 0; s < a.nstrands; s++) {
             s16x2 B[NP];
-            kadane_pairs<NP, QS>(lds, lane, lcodes + (r * 2 + s) * a.cw,
+            kadane_pairs<NP, QS, WIDE>(lds, lane, lcodes + (r * 2 + s) * a.cw,
                                  lqs + (r * 2 + s) * a.cq, m, a.xpool, a.dpool, B);
             if (partial_seg) {
 #pragma unroll
@@ -596,53 +660,83 @@ __global__ __launch_bounds__(256) void rescan_kernel(
 struct Tiles {
   int NP;
   bool qs;                 // quality mode (position-specific scores)
+  bool wide;               // scores may pass 31744: per-step max for B
   uint32_t R, ntiles, nchunks, nseg, grid;
   uint32_t win_slots, cw, cq;
   size_t lds;
 };
 
-template <int NP, bool QS>
-static maxss_status launch_scan(const ScanArgs& a, uint32_t grid, size_t lds, hipStream_t st) {
-  if (lds > 65536) {
-    maxss_status s = check_hip(hipFuncSetAttribute((const void*)scan_kernel<NP, QS>,
+// The scan kernel instance of (NP, quality mode, wide scores).
+template <bool QS, bool WIDE>
+static const void* scan_fn_np(int NP) {
+  if (NP == 8) return (const void*)scan_kernel<8, QS, WIDE>;
+  if (NP == 16) return (const void*)scan_kernel<16, QS, WIDE>;
+  return (const void*)scan_kernel<32, QS, WIDE>;
+}
+
+static const void* scan_fn(int NP, bool qs, bool wide) {
+  if (qs) return wide ? scan_fn_np<true, true>(NP) : scan_fn_np<true, false>(NP);
+  return wide ? scan_fn_np<false, true>(NP) : scan_fn_np<false, false>(NP);
+}
+
+template <int NP, bool QS, bool WIDE>
+static void launch_np(const ScanArgs& a, uint32_t grid, size_t lds, hipStream_t st) {
+  scan_kernel<NP, QS, WIDE><<<grid, 64, lds, st>>>(a);
+}
+
+template <bool QS, bool WIDE>
+static void launch_qw(int NP, const ScanArgs& a, uint32_t grid, size_t lds, hipStream_t st) {
+  if (NP == 8) launch_np<8, QS, WIDE>(a, grid, lds, st);
+  else if (NP == 16) launch_np<16, QS, WIDE>(a, grid, lds, st);
+  else launch_np<32, QS, WIDE>(a, grid, lds, st);
+}
+
+static maxss_status launch_scan(const Tiles& t, const ScanArgs& a, hipStream_t st) {
+  if (t.lds > 65536) {
+    maxss_status s = check_hip(hipFuncSetAttribute(scan_fn(t.NP, t.qs, t.wide),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)lds),
+                                                   (int)t.lds),
                                "hipFuncSetAttribute(scan_kernel)");
     if (s) return s;
   }
   ProfScope prof("scan", st);
-  scan_kernel<NP, QS><<<grid, 64, lds, st>>>(a);
+  if (t.qs) {
+    if (t.wide) launch_qw<true, true>(t.NP, a, t.grid, t.lds, st);
+    else launch_qw<true, false>(t.NP, a, t.grid, t.lds, st);
+  } else {
+    if (t.wide) launch_qw<false, true>(t.NP, a, t.grid, t.lds, st);
+    else launch_qw<false, false>(t.NP, a, t.grid, t.lds, st);
+  }
   return check_hip(hipGetLastError(), "scan_kernel");
 }
 
-// Resident scan waves per CU for (NP, LDS bytes), queried once per shape and
-// cached, so that a step being captured into a graph makes no runtime query.
-template <int NP, bool QS>
-static hipError_t occupancy_query(int* blocks, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, scan_kernel<NP, QS>, 64, lds);
-}
-
-static int occupancy_for(int NP, bool qs, size_t lds) {
+// Resident scan waves per CU for (kernel instance, LDS bytes), queried once
+// per shape and cached, so that a step being captured into a graph makes no
+// runtime query.
+static int occupancy_for(int NP, bool qs, bool wide, size_t lds) {
   static std::mutex mu;
   static std::map<std::pair<int, size_t>, int> cache;
   std::lock_guard<std::mutex> g(mu);
-  const int key = NP * 2 + (qs ? 1 : 0);
+  const int key = NP * 4 + (qs ? 2 : 0) + (wide ? 1 : 0);
   auto it = cache.find({key, lds});
   if (it != cache.end()) return it->second;
   int blocks = 0;
-  hipError_t e;
-  switch (key) {
-    case 16: e = occupancy_query<8, false>(&blocks, lds); break;
-    case 17: e = occupancy_query<8, true>(&blocks, lds); break;
-    case 32: e = occupancy_query<16, false>(&blocks, lds); break;
-    case 33: e = occupancy_query<16, true>(&blocks, lds); break;
-    case 64: e = occupancy_query<32, false>(&blocks, lds); break;
-    default: e = occupancy_query<32, true>(&blocks, lds); break;
-  }
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_fn(NP, qs, wide), 64, lds);
   if (e != hipSuccess || blocks < 1) blocks = 1;
   cache[{key, lds}] = blocks;
   return blocks;
 }
+
+// Largest score a window can reach (every scored base a match).
+static uint64_t score_bound(const Index* ix) {
+  const uint64_t scale = qual_mode(ix) ? ix->p.qual_scale : 1u;
+  return (uint64_t)ix->p.max_read_len * (uint64_t)(int64_t)ix->p.match * scale;
+}
+
+// Scores up to this bound keep the biased values (0x8000 + h) at or below
+// 0xFC00, binary16 -infinity, where their minimum3 order is that of h.
+static constexpr uint64_t kNarrowScoreMax = 31744;
 
 // Per-wave LDS budget of the scan: the genome window plus the tile's codes.
 static constexpr size_t kScanLdsBudget = 40 * 1024;
@@ -669,6 +763,7 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
   t.win_slots = win_slots_for(t.NP, mstride);
   t.cw = mstride / 8 + (uint32_t)t.NP / 8 + 1;
   t.qs = qual_mode(ix);
+  t.wide = score_bound(ix) > kNarrowScoreMax;
   t.cq = t.qs ? (mstride / scan_step(ix) + 1) / 2 + 1 : 0u;
   const size_t win_bytes = (size_t)t.win_slots * 4u;
   const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
@@ -677,7 +772,8 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
   if (win_bytes + rmax * per_read > 64 * 1024 && rmax > 1) rmax = 1;
   t.R = force->R ? (force->R < rmax ? force->R : rmax) : rmax;
   t.lds = win_bytes + t.R * per_read;
-  const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.lds);
+  const uint32_t resident =
+      (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.wide, t.lds);
   if (!force->R)
     while (t.R > 4 && (uint64_t)((n + t.R - 1) / t.R) * ix->NF < 4ull * resident) t.R /= 2;
   t.lds = win_bytes + t.R * per_read;
@@ -794,7 +890,8 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
     t.R = 1;
     const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
     t.lds = (size_t)t.win_slots * 4u + per_read;
-    const uint32_t resident = (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.lds);
+    const uint32_t resident =
+      (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.wide, t.lds);
     t.ntiles = n;
     uint64_t want = (8ull * resident + n - 1) / n;
     if (want < 1) want = 1;
@@ -834,15 +931,7 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   a.qsc = t.qs ? er.qsc : nullptr;
   a.cq = t.cq;
   if (t.qs && !er.qsc) return fail(MAXSS_ESTATE, "quality mode without position scores");
-  if (t.qs) {
-    if (t.NP == 8) s = launch_scan<8, true>(a, t.grid, t.lds, st);
-    else if (t.NP == 16) s = launch_scan<16, true>(a, t.grid, t.lds, st);
-    else s = launch_scan<32, true>(a, t.grid, t.lds, st);
-  } else {
-    if (t.NP == 8) s = launch_scan<8, false>(a, t.grid, t.lds, st);
-    else if (t.NP == 16) s = launch_scan<16, false>(a, t.grid, t.lds, st);
-    else s = launch_scan<32, false>(a, t.grid, t.lds, st);
-  }
+  s = launch_scan(t, a, st);
   if (s) return s;
   {
     ProfScope prof("merge", st);

@@ -53,6 +53,26 @@ def test_quality_scan_every_tile_shape(F):
     ix.close()
 
 
+@pytest.mark.parametrize("mlen", [253, 300])
+def test_quality_scan_score_bound_both_kernels(mlen):
+    # match * qual_scale = 125: max_read_len 253 keeps the bound at 31625
+    # (two-step kernels), 300 raises it to 37500 (per-step kernels)
+    seq, r, q = _case(23)
+    long_ = gen.sample_reads(gen.Genome(seq, "q"), 6, 29, [mlen], 0.0, 0.1)
+    qs = gen.sample_qualities(long_, 31)
+    reads = [r.read(i) for i in range(r.n)] + [long_.read(i) for i in range(long_.n)]
+    quals = [q[int(r.offsets[i]):int(r.offsets[i + 1])] for i in range(r.n)] + \
+        [qs[int(long_.offsets[i]):int(long_.offsets[i + 1])] for i in range(long_.n)]
+    off = np.zeros(len(reads) + 1, np.uint64)
+    off[1:] = np.cumsum([len(x) for x in reads])
+    rs = np.frombuffer(b"".join(reads), np.uint8)
+    qq = np.concatenate(quals)
+    ref = oracle.scan(seq, 2048, rs, off, 5, -4, nthreads=8, quals=qq, qscale=25)
+    ix = mx.Index(seq, 2048, mlen, 5, -4, GAP, qual_scale=25)
+    assert_same(ix.scan(rs, off, qual=qq), ref, "max_read_len %d" % mlen)
+    ix.close()
+
+
 def test_quality_device_reads_and_invalid_quality():
     torch = _torch()
     seq, r, q = _case(17)

@@ -167,6 +167,24 @@ def test_max_score_range_limit():
     assert got["score"][0][0] == 8191 * 8
 
 
+@pytest.mark.parametrize("np_", [8, 16, 32])
+def test_narrow_score_range_limit(np_):
+    # max_read_len * match = 31744: the largest bound that takes the two-step
+    # kernels (a full-length exact copy scores 0xFC00 - 0x8000 in biased form)
+    g = gen.uniform_genome(12_000, 31)
+    read = g.seq[700:700 + 3968].tobytes()
+    mut = bytearray(read[:3000])
+    mut[1500] = ord("A") if mut[1500] != ord("A") else ord("C")
+    s, off = csr([read, bytes(mut), read[:1]])
+    ix = mx.Index(g.seq, 4096, 3968, 8, -8)
+    mx.maxss_index_set_tiles(ix.handle, np_, 0, 0)
+    got = ix.scan(s, off)
+    ref = oracle.scan(g.seq, 4096, s, off, 8, -8, nthreads=2)
+    ix.close()
+    assert_same(got, ref, "narrow range NP=%d" % np_)
+    assert got["score"][0][0] == 31744
+
+
 def test_device_invalid_reads_marked():
     torch = _torch()
     g = gen.uniform_genome(10_000, 29)
