@@ -25,10 +25,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 CU, SIMD_LANES, CLOCK = 256, 64, 2.4e9          # 256 CUs x 4 SIMD16 = 64 lanes/clk/CU
 INT16_PACKED_OPS = CU * SIMD_LANES * CLOCK * 2   # 16-bit lane ops/s with packed math
-# 16-bit lane ops per cell of the scan's inner loop on these workloads (score
-# bound <= 31744): score select and saturating add (Kadane's add + clamp) every
-# step, one three-way running max per two steps
-OPS_PER_CELL = 2.5
 
 
 def recorded_traffic(workload: str):
@@ -351,7 +347,11 @@ def main():
     ms_step = dt / args.steps * 1e3
     gcups = cells / (dt / args.steps) / 1e9
     scan_s = scan_ms / max(scan_k, 1) / 1e3
-    achieved = OPS_PER_CELL * cells / scan_s / 1e12
+    # 16-bit lane ops per cell of the launched kernel's inner loop (score
+    # select, saturating add, running max; the library reports the variant)
+    knp, kind = ix.kernel_info()
+    ops_per_cell = mx.KERNEL_OPS_PER_CELL[kind]
+    achieved = ops_per_cell * cells / scan_s / 1e12
     peak = INT16_PACKED_OPS / 1e12
     res = {
         "metric": "MaxSS GCUPS; reads/s, learned-proposal vs full scan at >=99% top-1 agreement",
@@ -385,6 +385,8 @@ def main():
             "unit": "Tops/s",
             "frac": round(achieved / peak, 4),
             "traffic": recorded_traffic(w.name),
+            "kernel": {"np": knp, "variant": ["step-max", "two-step", "register-bank"][kind],
+                       "ops_per_cell": ops_per_cell},
         },
     }
     if tune is not None:

@@ -253,6 +253,25 @@ typedef struct {
 maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sample, const char* cache_path,
                             maxss_tune_result* result);
 
+/* Scan kernel variants, by the cost of their Kadane inner loop per packed
+ * pair of 16-bit cells and step (maxss_scan_kernel_info):
+ *   STEP_MAX       score select, saturating add and running max: 3 VALU
+ *                  instructions (score bounds above 31744);
+ *   TWO_STEP       select and add, one three-way max per two steps: 2.5;
+ *   REGISTER_BANK  the four per-base score pairs of every window word kept
+ *                  in registers (one v_perm_b32 each when the word enters):
+ *                  add, half a max, a quarter of a select: 1.75
+ *                  (16 offsets pairs per lane, plain scores). */
+#define MAXSS_KERNEL_STEP_MAX 0
+#define MAXSS_KERNEL_TWO_STEP 1
+#define MAXSS_KERNEL_REGISTER_BANK 2
+
+/* The offset pairs per lane (np) and the kernel variant (kind) that the next
+ * scan on the index launches with its current tile setting (built-in,
+ * maxss_index_set_tiles or maxss_autotune).  Output pointers may be NULL.
+ * Errors: EINVAL on a NULL index. */
+maxss_status maxss_scan_kernel_info(const maxss_index* index, int32_t* np, int32_t* kind);
+
 /* Force a tile shape (np 0/8/16/32, reads_per_tile 0..64, rounds 0..1024;
  * 0 = built-in).  Results never depend on it.  Errors: EINVAL. */
 maxss_status maxss_index_set_tiles(maxss_index* index, int32_t np, uint32_t reads_per_tile,

@@ -25,6 +25,10 @@ MAXSS_ESTATE = -5
 MAXSS_ONE_STRAND = 1
 MAXSS_NW_GLOBAL = 2
 MAXSS_FAST = 4
+# scan kernel variants (maxss_scan_kernel_info), by VALU instructions per packed
+# cell pair and step of their inner loop
+MAXSS_KERNEL_STEP_MAX, MAXSS_KERNEL_TWO_STEP, MAXSS_KERNEL_REGISTER_BANK = 0, 1, 2
+KERNEL_OPS_PER_CELL = {0: 3.0, 1: 2.5, 2: 1.75}
 MAXSS_READ_INVALID = -2
 MAXSS_ALN_TRUNCATED = 1
 MAXSS_ALN_SKIPPED = 2
@@ -66,6 +70,7 @@ class Reads(ctypes.Structure):
 EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_scan_reads",
            "maxss_align_top", "maxss_plan_create", "maxss_plan_free", "maxss_plan_run",
            "maxss_plan_run_graph", "maxss_autotune", "maxss_index_set_tiles",
+           "maxss_scan_kernel_info",
            "maxss_model_create", "maxss_model_free", "maxss_model_get_params", "maxss_model_save",
            "maxss_model_load", "maxss_profiles", "maxss_proposal_scores",
            "maxss_proposal_candidates", "maxss_scan_reads_proposed", "maxss_model_train_step",
@@ -116,6 +121,8 @@ def lib():
                                      c.POINTER(TuneResult)]
         L.maxss_index_set_tiles.restype = c.c_int
         L.maxss_index_set_tiles.argtypes = [c.c_void_p, c.c_int32, c.c_uint32, c.c_uint32]
+        L.maxss_scan_kernel_info.restype = c.c_int
+        L.maxss_scan_kernel_info.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p]
         L.maxss_model_create.restype = c.c_int
         L.maxss_model_create.argtypes = [c.c_void_p, c.POINTER(c.c_void_p)]
         L.maxss_model_free.restype = None
@@ -352,6 +359,13 @@ def maxss_index_set_tiles(handle, np_: int = 0, reads_per_tile: int = 0, rounds:
     _check(lib().maxss_index_set_tiles(h_(handle), np_, reads_per_tile, rounds))
 
 
+def maxss_scan_kernel_info(handle):
+    """(offset pairs per lane, kernel variant) of the next scan on the index."""
+    np_, kind = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().maxss_scan_kernel_info(h_(handle), ctypes.byref(np_), ctypes.byref(kind)))
+    return np_.value, kind.value
+
+
 def maxss_mapq(top, n: int, mapq, mapped=None, ratio_num: int = 9, ratio_den: int = 10,
                min_mapq: int = -1, stream=None) -> None:
     """Mapping quality of n top-2 records (device tensors: top n*32 bytes,
@@ -525,6 +539,9 @@ class Index:
 
     def set_tiles(self, np_: int = 0, reads_per_tile: int = 0, rounds: int = 0):
         maxss_index_set_tiles(self.handle, np_, reads_per_tile, rounds)
+
+    def kernel_info(self):
+        return maxss_scan_kernel_info(self.handle)
 
     def autotune(self, seq, offsets, cache_path=None, qual=None):
         return maxss_autotune(self.handle, seq, offsets, cache_path, qual)

@@ -28,6 +28,12 @@
 //     H'_t+1) (the biased values read as binary16 fall as h grows), so each
 //     pair of cells costs five VALU instructions per two steps; above it,
 //     B' = max(B', H') is one v_pk_max_i16 per step (three per step).
+//   * NP = 16 with plain scores (scan_kernel_bank): the select moves out of
+//     the loop.  The four per-base score pairs of every window word are
+//     built once, when the word enters the register window, and a step
+//     reads the bank of its read base through the VGPR index mode, so the
+//     loop is 1.75 instructions per pair and step (add, half a minimum3, a
+//     quarter of a v_perm_b32).
 //   * The window of selector words a lane needs slides by one per step; it is
 //     kept in registers (2*NP words) and refilled from LDS every NP steps.
 //   * A persistent grid pulls (read tile x fragment chunk) work items from an
@@ -346,18 +352,271 @@ __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t l
   if (rem & 1) kadane_sub<NP, 1, QS, WIDE>(lds, lbase, lc, lq, k, xpool, dpool, H, B);
 }
 
+// ---------------------------------------------------------------------------
+// Register-bank Kadane (NP = 16, plain scores, score bound <= 31744).
+//
+// For each of the lane's 32 window words (the current block's 16 and the
+// next block's 16) and each read base b in {A, C, G, T}, the pair of scores
+// sigma(b, genome) is computed once, when the word enters the window, by one
+// v_perm_b32 from b's score pool: 128 bank registers, bank b holding slot s
+// in v[64 + 32 b + s].  A Kadane step then has no select: with the VGPR
+// index mode set to 32 b on source 0 for the step's read base b, one
+// v_pk_add_i16 per offset pair reads the right bank.  A read N mismatches
+// every genome base, so its steps add the constant pair (X, X) (a branch on
+// the uniform code).  Per offset pair and two steps: two adds and one
+// minimum3, plus four perms per window word, i.e. per 16 pairs.
+//
+// Register map: banks v64..v191, H v192..v207, T (the value after an even
+// step) v208..v223, B v224..v239, staging of the words that enter the window
+// v240..v255.  The kernels that use these helpers limit the compiler to
+// v0..v63 (amdgpu_num_vgpr), so the state persists between the asm
+// statements below; each statement lists the registers it touches as
+// clobbers, so that the kernel allocates them.  M0, which the index mode
+// overwrites, is saved and restored inside each statement.
+
+#pragma clang diagnostic push
+// v64..v255 are outside the compiler's range in the bank kernel; listing them
+// as clobbers is what makes the kernel allocate them.
+#pragma clang diagnostic ignored "-Winline-asm"
+#define MAXSS_V10(p) p "0", p "1", p "2", p "3", p "4", p "5", p "6", p "7", p "8", p "9"
+#define MAXSS_BANK_CLOBBERS                                                               \
+  "v64", "v65", "v66", "v67", "v68", "v69", MAXSS_V10("v7"), MAXSS_V10("v8"),            \
+      MAXSS_V10("v9"), MAXSS_V10("v10"), MAXSS_V10("v11"), MAXSS_V10("v12"),             \
+      MAXSS_V10("v13"), MAXSS_V10("v14"), MAXSS_V10("v15"), MAXSS_V10("v16"),            \
+      MAXSS_V10("v17"), MAXSS_V10("v18"), MAXSS_V10("v19"), MAXSS_V10("v20"),            \
+      MAXSS_V10("v21"), MAXSS_V10("v22"), MAXSS_V10("v23"), MAXSS_V10("v24"), "v250",    \
+      "v251", "v252", "v253", "v254", "v255"
+
+#define MAXSS_IRP16 "0,1,2,3,4,5,6,7,8,9,10,11,12,13,14,15"
+
+// One Kadane step t of the block (index mode on source 0 for the step's read
+// base; the N branch adds (X, X) out of line).  Even steps write T, odd
+// steps write H and fold both into B with one minimum3.
+#define MAXSS_BANK_STEP(L)                                                        \
+  ".if \\t < 8\n"                                                                 \
+  "s_bfe_u32 %[sc], %[c0], (4*\\t)|0x40000\n"                                     \
+  ".else\n"                                                                       \
+  "s_bfe_u32 %[sc], %[c1], (4*(\\t-8))|0x40000\n"                                 \
+  ".endif\n"                                                                      \
+  "s_cmp_eq_u32 %[sc], 4\n"                                                       \
+  "s_cbranch_scc1 .L" L "N%=_\\t\n"                                               \
+  "s_and_b32 %[sc], %[sc], 6\n"                                                   \
+  "s_lshl_b32 %[sc], %[sc], 4\n"                                                  \
+  "s_set_gpr_idx_on %[sc], gpr_idx(SRC0)\n"                                       \
+  "s_nop 0\n"                                                                     \
+  ".irp j, " MAXSS_IRP16 "\n"                                                     \
+  ".if (\\t & 1) == 0\n"                                                          \
+  "v_pk_add_i16 v[208+\\j], v[64+((\\j+\\t+%[f])&31)], v[192+\\j] clamp\n"        \
+  ".else\n"                                                                       \
+  "v_pk_add_i16 v[192+\\j], v[64+((\\j+\\t+%[f])&31)], v[208+\\j] clamp\n"        \
+  ".endif\n"                                                                      \
+  ".endr\n"                                                                       \
+  "s_set_gpr_idx_off\n"                                                           \
+  ".L" L "R%=_\\t:\n"                                                             \
+  ".if (\\t & 1) == 1\n"                                                          \
+  ".irp j, " MAXSS_IRP16 "\n"                                                     \
+  "v_pk_minimum3_f16 v[224+\\j], v[224+\\j], v[208+\\j], v[192+\\j]\n"            \
+  ".endr\n"                                                                       \
+  ".endif\n"
+
+// The out-of-line N steps of MAXSS_BANK_STEP.
+#define MAXSS_BANK_NSTEP(L)                                                       \
+  ".L" L "N%=_\\t:\n"                                                             \
+  ".irp j, " MAXSS_IRP16 "\n"                                                     \
+  ".if (\\t & 1) == 0\n"                                                          \
+  "v_pk_add_i16 v[208+\\j], %[xx], v[192+\\j] clamp\n"                            \
+  ".else\n"                                                                       \
+  "v_pk_add_i16 v[192+\\j], %[xx], v[208+\\j] clamp\n"                            \
+  ".endif\n"                                                                      \
+  ".endr\n"                                                                       \
+  "s_branch .L" L "R%=_\\t\n"
+
+// The four bank words of window slot S from the staged selector word W.
+#define MAXSS_BANK_FILL(S, W)                                                     \
+  "v_perm_b32 v[64+" S "], %[h0], %[l0], v[240+" W "]\n"                          \
+  "v_perm_b32 v[96+" S "], %[h1], %[l1], v[240+" W "]\n"                          \
+  "v_perm_b32 v[128+" S "], %[h2], %[l2], v[240+" W "]\n"                         \
+  "v_perm_b32 v[160+" S "], %[h3], %[l3], v[240+" W "]\n"
+
+#define MAXSS_BANK_POOLS                                                          \
+  [l0] "v"(pl[0]), [l1] "v"(pl[1]), [l2] "v"(pl[2]), [l3] "v"(pl[3]), [h0] "s"(ph[0]), \
+      [h1] "s"(ph[1]), [h2] "s"(ph[2]), [h3] "s"(ph[3])
+
+__device__ inline uint32_t lds_byte_addr(const uint32_t* p) {
+  typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+  return (uint32_t)(uintptr_t)(lds_u32*)p;
+}
+
+// H = B = 0 (biased) and the banks of window words 0..31 (LDS words at byte
+// address la: words 0..15, then a pad word, then words 16..31).
+__device__ inline void bank_init(uint32_t la, const uint32_t (&pl)[4], const uint32_t (&ph)[4]) {
+  asm volatile(
+      ".irp i, 0,2,4,6,8,10,12,14\n"
+      "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:\\i offset1:\\i+1\n"
+      ".endr\n"
+      ".irp j, " MAXSS_IRP16 "\n"
+      "v_mov_b32 v[192+\\j], 0x80008000\n"
+      "v_mov_b32 v[224+\\j], 0x80008000\n"
+      ".endr\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      ".irp s, " MAXSS_IRP16 "\n" MAXSS_BANK_FILL("\\s", "\\s") ".endr\n"
+      ".irp i, 0,2,4,6,8,10,12,14\n"
+      "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:17+\\i offset1:18+\\i\n"
+      ".endr\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      ".irp s, " MAXSS_IRP16 "\n" MAXSS_BANK_FILL("16+\\s", "\\s") ".endr\n"
+      :
+      : [la] "v"(la), MAXSS_BANK_POOLS
+      : "memory", MAXSS_BANK_CLOBBERS);
+}
+
+// One block of 16 steps whose current window words sit in slots FIRST..
+// FIRST+15 (the next block's in the other 16).  The 16 words that replace
+// the current ones (LDS byte address la) are staged at the start and fill
+// slot FIRST+s four steps after its last use (slots 12..15 at the end).
+// c0, c1: the 4-bit codes of the 16 read positions.
+template <int FIRST>
+__device__ inline void bank_block(uint32_t c0, uint32_t c1, uint32_t la,
+                                  const uint32_t (&pl)[4], const uint32_t (&ph)[4],
+                                  uint32_t xx) {
+  uint32_t sc, sm;
+  asm volatile(
+      "s_mov_b32 %[sm], m0\n"
+      ".irp i, 0,2,4,6,8,10,12,14\n"
+      "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:\\i offset1:\\i+1\n"
+      ".endr\n"
+      ".irp t, " MAXSS_IRP16 "\n"
+      MAXSS_BANK_STEP("b")
+      ".if \\t == 4\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      ".endif\n"
+      ".if \\t >= 4\n" MAXSS_BANK_FILL("%[f]+\\t-4", "\\t-4") ".endif\n"
+      ".endr\n"
+      ".irp s, 12,13,14,15\n" MAXSS_BANK_FILL("%[f]+\\s", "\\s") ".endr\n"
+      "s_branch .LbE%=\n"
+      ".irp t, " MAXSS_IRP16 "\n" MAXSS_BANK_NSTEP("b") ".endr\n"
+      ".LbE%=:\n"
+      "s_mov_b32 m0, %[sm]\n"
+      : [sc] "=&s"(sc), [sm] "=&s"(sm)
+      : [c0] "s"(c0), [c1] "s"(c1), [la] "v"(la), [xx] "s"(xx), [f] "n"(FIRST),
+        MAXSS_BANK_POOLS
+      : "scc", "memory", MAXSS_BANK_CLOBBERS);
+}
+
+// The last rem (1..15) steps of the read, window in slots FIRST.. as in
+// bank_block, no reloads.  An even last step folds T into B on exit.
+template <int FIRST>
+__device__ inline void bank_tail(uint32_t c0, uint32_t c1, uint32_t rem, uint32_t xx) {
+  uint32_t sc, sm;
+  asm volatile(
+      "s_mov_b32 %[sm], m0\n"
+      ".irp t, 0,1,2,3,4,5,6,7,8,9,10,11,12,13,14\n"
+      MAXSS_BANK_STEP("t")
+      "s_cmp_eq_u32 %[rem], \\t+1\n"
+      ".if (\\t & 1) == 0\n"
+      "s_cbranch_scc1 .LtX%=\n"
+      ".else\n"
+      "s_cbranch_scc1 .LtE%=\n"
+      ".endif\n"
+      ".endr\n"
+      "s_branch .LtE%=\n"
+      ".irp t, 0,1,2,3,4,5,6,7,8,9,10,11,12,13,14\n" MAXSS_BANK_NSTEP("t") ".endr\n"
+      ".LtX%=:\n"
+      ".irp j, " MAXSS_IRP16 "\n"
+      "v_pk_minimum3_f16 v[224+\\j], v[224+\\j], v[208+\\j], v[208+\\j]\n"
+      ".endr\n"
+      ".LtE%=:\n"
+      "s_mov_b32 m0, %[sm]\n"
+      : [sc] "=&s"(sc), [sm] "=&s"(sm)
+      : [c0] "s"(c0), [c1] "s"(c1), [rem] "s"(rem), [xx] "s"(xx), [f] "n"(FIRST)
+      : "scc", MAXSS_BANK_CLOBBERS);
+}
+
+__device__ inline void bank_extract(s16x2 (&B)[16]) {
+  uint32_t o[16];
+  asm volatile(
+      "v_mov_b32 %[o0], v224\n v_mov_b32 %[o1], v225\n v_mov_b32 %[o2], v226\n"
+      "v_mov_b32 %[o3], v227\n v_mov_b32 %[o4], v228\n v_mov_b32 %[o5], v229\n"
+      "v_mov_b32 %[o6], v230\n v_mov_b32 %[o7], v231\n v_mov_b32 %[o8], v232\n"
+      "v_mov_b32 %[o9], v233\n v_mov_b32 %[o10], v234\n v_mov_b32 %[o11], v235\n"
+      "v_mov_b32 %[o12], v236\n v_mov_b32 %[o13], v237\n v_mov_b32 %[o14], v238\n"
+      "v_mov_b32 %[o15], v239\n"
+      : [o0] "=v"(o[0]), [o1] "=v"(o[1]), [o2] "=v"(o[2]), [o3] "=v"(o[3]), [o4] "=v"(o[4]),
+        [o5] "=v"(o[5]), [o6] "=v"(o[6]), [o7] "=v"(o[7]), [o8] "=v"(o[8]), [o9] "=v"(o[9]),
+        [o10] "=v"(o[10]), [o11] "=v"(o[11]), [o12] "=v"(o[12]), [o13] "=v"(o[13]),
+        [o14] "=v"(o[14]), [o15] "=v"(o[15]));
+#pragma unroll
+  for (int j = 0; j < 16; j++) B[j] = __builtin_bit_cast(s16x2, o[j]);
+}
+
+// Kadane over one read strand of length m for this lane's 16 offset pairs
+// with the register banks (same window layout and code words as
+// kadane_pairs<16, ...>).  xx: the pair (X, X).
+__device__ inline void kadane_pairs_bank(const uint32_t* __restrict__ lds, uint32_t lane,
+                                         const uint32_t* __restrict__ lc, uint32_t m,
+                                         uint64_t xpool, uint64_t dpool, uint32_t xx,
+                                         s16x2 (&B)[16]) {
+  constexpr uint32_t NP = 16;
+  uint32_t pl[4], ph[4];
+#pragma unroll
+  for (int b = 0; b < 4; b++) {
+    const uint64_t pool = xpool ^ (dpool << (8 * (2 * b + 1)));
+    pl[b] = (uint32_t)pool;
+    ph[b] = (uint32_t)(pool >> 32);
+  }
+  const uint32_t la = lds_byte_addr(lds + lane * (NP + 1));
+  bank_init(la, pl, ph);
+  const uint32_t mfull = m / NP * NP;
+  // codes of the next block are read before the current block's asm, so the
+  // LDS latency hides behind it
+  uint32_t n0 = lc[0], n1 = lc[1];
+  uint32_t kb = 0, pb = 0;
+  for (; kb + 2 * NP <= mfull; kb += 2 * NP, pb += 2 * (NP + 1)) {
+    uint32_t c0 = __builtin_amdgcn_readfirstlane(n0), c1 = __builtin_amdgcn_readfirstlane(n1);
+    n0 = lc[(kb + NP) / 8];
+    n1 = lc[(kb + NP) / 8 + 1];
+    bank_block<0>(c0, c1, la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
+    c0 = __builtin_amdgcn_readfirstlane(n0);
+    c1 = __builtin_amdgcn_readfirstlane(n1);
+    n0 = lc[(kb + 2 * NP) / 8];
+    n1 = lc[(kb + 2 * NP) / 8 + 1];
+    bank_block<16>(c0, c1, la + 4u * (pb + 3 * (NP + 1)), pl, ph, xx);
+  }
+  bool odd = false;
+  if (kb < mfull) {
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(n0),
+                   c1 = __builtin_amdgcn_readfirstlane(n1);
+    n0 = lc[(kb + NP) / 8];
+    n1 = lc[(kb + NP) / 8 + 1];
+    bank_block<0>(c0, c1, la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
+    odd = true;
+  }
+  const uint32_t rem = m - mfull;
+  if (rem) {
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(n0),
+                   c1 = __builtin_amdgcn_readfirstlane(n1);
+    if (odd) bank_tail<16>(c0, c1, rem, xx);
+    else bank_tail<0>(c0, c1, rem, xx);
+  }
+  bank_extract(B);
+}
+#pragma clang diagnostic pop
+
 __device__ inline int wave_max_i32(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
 }
 
-template <int NP, bool QS, bool WIDE>
-__global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
+template <int NP, bool QS, bool WIDE, bool BANK>
+__device__ __forceinline__ void scan_body(const ScanArgs& a) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t HALF = 64u * NP, S = 128u * NP;
   const uint32_t lane = threadIdx.x;
   uint32_t* lcodes = lds + a.win_slots;
+  // (X, X) as two int16 (the pool's byte 0 is X)
+  const uint32_t xx = (uint32_t)(uint16_t)(int16_t)(int8_t)(a.xpool & 0xFFu) * 0x10001u;
+  (void)xx;
   uint32_t* lqs = lcodes + a.R * 2 * a.cw;  // quality mode: position-score pairs
   for (;;) {
     uint32_t w = 0;
@@ -440,8 +699,12 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
           uint32_t bm = 0x80008000u;
           for (uint32_t s = 0; s < a.nstrands; s++) {
             s16x2 B[NP];
-            kadane_pairs<NP, QS, WIDE>(lds, lane, lcodes + (r * 2 + s) * a.cw,
-                                 lqs + (r * 2 + s) * a.cq, m, a.xpool, a.dpool, B);
+            if constexpr (BANK)
+              kadane_pairs_bank(lds, lane, lcodes + (r * 2 + s) * a.cw, m, a.xpool, a.dpool,
+                                xx, B);
+            else
+              kadane_pairs<NP, QS, WIDE>(lds, lane, lcodes + (r * 2 + s) * a.cw,
+                                         lqs + (r * 2 + s) * a.cq, m, a.xpool, a.dpool, B);
             if (partial_seg) {
 #pragma unroll
               for (int j = 0; j < NP; j++) {
@@ -473,6 +736,18 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
     }
     if (lane < rcount) a.partial[(uint64_t)my_read * a.nchunks + chunk] = make_int4(t1s, t1f, t2s, t2f);
   }
+}
+
+template <int NP, bool QS, bool WIDE>
+__global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
+  scan_body<NP, QS, WIDE, false>(a);
+}
+
+// NP = 16, plain scores, score bound <= 31744: the register-bank Kadane, with
+// the compiler confined to v0..v63 so that v64..v255 hold the banks.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_num_vgpr(32))) void scan_kernel_bank(
+    ScanArgs a) {
+  scan_body<16, false, false, true>(a);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint32_t n) {
@@ -670,7 +945,10 @@ struct Tiles {
 template <bool QS, bool WIDE>
 static const void* scan_fn_np(int NP) {
   if (NP == 8) return (const void*)scan_kernel<8, QS, WIDE>;
-  if (NP == 16) return (const void*)scan_kernel<16, QS, WIDE>;
+  if (NP == 16) {
+    if constexpr (!QS && !WIDE) return (const void*)scan_kernel_bank;
+    else return (const void*)scan_kernel<16, QS, WIDE>;
+  }
   return (const void*)scan_kernel<32, QS, WIDE>;
 }
 
@@ -681,7 +959,8 @@ static const void* scan_fn(int NP, bool qs, bool wide) {
 
 template <int NP, bool QS, bool WIDE>
 static void launch_np(const ScanArgs& a, uint32_t grid, size_t lds, hipStream_t st) {
-  scan_kernel<NP, QS, WIDE><<<grid, 64, lds, st>>>(a);
+  if constexpr (NP == 16 && !QS && !WIDE) scan_kernel_bank<<<grid, 64, lds, st>>>(a);
+  else scan_kernel<NP, QS, WIDE><<<grid, 64, lds, st>>>(a);
 }
 
 template <bool QS, bool WIDE>
@@ -744,6 +1023,8 @@ static constexpr size_t kScanLdsBudget = 40 * 1024;
 static int np_for(const Index* ix, const TileOverride* force) {
   const uint32_t F = parity_offsets(ix);
   if (force && (force->NP == 8 || force->NP == 16 || force->NP == 32)) return force->NP;
+  // plain scores within the narrow bound: NP = 16 runs the register-bank kernel
+  if (F % 2048 == 0 && !qual_mode(ix) && score_bound(ix) <= kNarrowScoreMax) return 16;
   if (F % 4096 == 0) return 32;
   if (F % 2048 == 0) return 16;
   return 8;
@@ -1037,4 +1318,18 @@ extern "C" maxss_status maxss_scan_reads(const maxss_index* index, const maxss_r
   release_reads(&dr, st);
   if (!reads->on_device && s == MAXSS_OK) s = check_hip(hipStreamSynchronize(st), "sync");
   return s;
+}
+
+extern "C" maxss_status maxss_scan_kernel_info(const maxss_index* index, int32_t* np,
+                                               int32_t* kind) {
+  clear_error();
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  if (!ix) return fail(MAXSS_EINVAL, "NULL index");
+  const int NP = np_for(ix, &ix->tune);
+  const bool qs = qual_mode(ix), wide = score_bound(ix) > kNarrowScoreMax;
+  if (np) *np = NP;
+  if (kind)
+    *kind = wide ? MAXSS_KERNEL_STEP_MAX
+                 : (NP == 16 && !qs ? MAXSS_KERNEL_REGISTER_BANK : MAXSS_KERNEL_TWO_STEP);
+  return MAXSS_OK;
 }

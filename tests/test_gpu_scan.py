@@ -125,8 +125,9 @@ def test_edge_shapes(G, F, lens):
     assert_same(got, ref, "G=%d F=%d" % (G, F))
 
 
-def test_n_runs_and_paper_scores():
-    got, ref = _edge_case(30_000, 512, [100] * 24, seed=5, M=5, X=-4, n_runs=40)
+@pytest.mark.parametrize("F", [512, 2048])
+def test_n_runs_and_paper_scores(F):
+    got, ref = _edge_case(30_000, F, [100] * 24, seed=5, M=5, X=-4, n_runs=40)
     assert_same(got, ref, "N runs, 5/-4")
 
 
@@ -141,14 +142,16 @@ def test_one_strand_flag():
     assert_same(got, ref, "one strand")
 
 
-def test_reads_with_n_and_all_n():
+@pytest.mark.parametrize("F", [1024, 2048])
+def test_reads_with_n_and_all_n(F):
     g = gen.uniform_genome(20_000, 17)
     reads = [b"N" * 50, b"ACGTN" * 10, g.seq[100:180].tobytes().replace(b"A", b"N"),
-             b"acgt" * 12, g.seq[5000:5100].tobytes().lower()]
+             b"acgt" * 12, g.seq[5000:5100].tobytes().lower(),
+             g.seq[7000:7037].tobytes()[:20] + b"N" + g.seq[7021:7037].tobytes()]
     s, off = csr(reads)
-    ix = mx.Index(g.seq, 1024, 100)
+    ix = mx.Index(g.seq, F, 100)
     got = ix.scan(s, off)
-    ref = oracle.scan(g.seq, 1024, s, off, nthreads=4)
+    ref = oracle.scan(g.seq, F, s, off, nthreads=4)
     ix.close()
     assert_same(got, ref, "N reads")
     assert got["score"][0].tolist() == [0, 0]
@@ -233,3 +236,19 @@ def test_bacterial_full_size_sampled():
     assert (got["score"][:, 0] >= got["score"][:, 1]).all()
     assert (got["score"][:, 0] <= 100).all() and (got["score"][:, 1] >= 0).all()
     assert (got["frag"][:, 0] != got["frag"][:, 1]).all()
+
+
+def test_kernel_info_follows_tiles_and_scores():
+    g = gen.uniform_genome(20_000, 37)
+    ix = mx.Index(g.seq, 2048, 100)
+    assert ix.kernel_info() == (16, mx.MAXSS_KERNEL_REGISTER_BANK)
+    ix.set_tiles(8, 0, 0)
+    assert ix.kernel_info() == (8, mx.MAXSS_KERNEL_TWO_STEP)
+    ix.set_tiles(0, 0, 0)
+    ix.close()
+    ix = mx.Index(g.seq, 4096, 4000, 8, -8)             # bound 32000 > 31744
+    assert ix.kernel_info() == (32, mx.MAXSS_KERNEL_STEP_MAX)
+    ix.close()
+    ix = mx.Index(g.seq, 2048, 100, 5, -4, -26, qual_scale=10)
+    assert ix.kernel_info() == (16, mx.MAXSS_KERNEL_TWO_STEP)
+    ix.close()
