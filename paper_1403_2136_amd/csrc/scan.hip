@@ -389,37 +389,71 @@ __device__ inline void kadane_pairs(const uint32_t* __restrict__ lds, uint32_t l
 
 #define MAXSS_IRP16 "0,1,2,3,4,5,6,7,8,9,10,11,12,13,14,15"
 
-// One Kadane step t of the block (index mode on source 0 for the step's read
-// base; the N branch adds (X, X) out of line).  Even steps write T, odd
-// steps write H and fold both into B with one minimum3.
-#define MAXSS_BANK_STEP(L)                                                        \
-  ".if \\t < 8\n"                                                                 \
-  "s_bfe_u32 %[sc], %[c0], (4*\\t)|0x40000\n"                                     \
-  ".else\n"                                                                       \
-  "s_bfe_u32 %[sc], %[c1], (4*(\\t-8))|0x40000\n"                                 \
-  ".endif\n"                                                                      \
-  "s_cmp_eq_u32 %[sc], 4\n"                                                       \
-  "s_cbranch_scc1 .L" L "N%=_\\t\n"                                               \
-  "s_and_b32 %[sc], %[sc], 6\n"                                                   \
-  "s_lshl_b32 %[sc], %[sc], 4\n"                                                  \
-  "s_set_gpr_idx_on %[sc], gpr_idx(SRC0)\n"                                       \
-  "s_nop 0\n"                                                                     \
+// The read codes reach these helpers as bytes 16c (c = 1, 3, 5, 7 for A, C,
+// G, T; 4 for N), four per word.  16c = 32b + 16 for base b, so an add that
+// names v[48 + slot] reads bank b at v[64 + 32b + slot] when the index is
+// the code byte itself; s_set_gpr_idx_on takes the low byte of its operand.
+
+// Code word of step t (c0..c3 hold steps 0-3, 4-7, 8-11, 12-15), and an
+// instruction PRE cN POST on it.
+#define MAXSS_BANK_CW                                                             \
+  ".if \\t < 4\n.set maxss_cwn, 0\n.elseif \\t < 8\n.set maxss_cwn, 1\n"          \
+  ".elseif \\t < 12\n.set maxss_cwn, 2\n.else\n.set maxss_cwn, 3\n.endif\n"
+#define MAXSS_SEL4(PRE, POST)                                                     \
+  ".if maxss_cwn == 0\n" PRE "%[c0]" POST "\n"                                    \
+  ".elseif maxss_cwn == 1\n" PRE "%[c1]" POST "\n"                                \
+  ".elseif maxss_cwn == 2\n" PRE "%[c2]" POST "\n"                                \
+  ".else\n" PRE "%[c3]" POST "\n.endif\n"
+
+// The adds of step t (even: T = bank + H; odd: H = bank + T), index mode on.
+#define MAXSS_BANK_ADDS                                                           \
   ".irp j, " MAXSS_IRP16 "\n"                                                     \
   ".if (\\t & 1) == 0\n"                                                          \
-  "v_pk_add_i16 v[208+\\j], v[64+((\\j+\\t+%[f])&31)], v[192+\\j] clamp\n"        \
+  "v_pk_add_i16 v[208+\\j], v[48+((\\j+\\t+%[f])&31)], v[192+\\j] clamp\n"        \
   ".else\n"                                                                       \
-  "v_pk_add_i16 v[192+\\j], v[64+((\\j+\\t+%[f])&31)], v[208+\\j] clamp\n"        \
+  "v_pk_add_i16 v[192+\\j], v[48+((\\j+\\t+%[f])&31)], v[208+\\j] clamp\n"        \
   ".endif\n"                                                                      \
-  ".endr\n"                                                                       \
-  "s_set_gpr_idx_off\n"                                                           \
-  ".L" L "R%=_\\t:\n"                                                             \
-  ".if (\\t & 1) == 1\n"                                                          \
+  ".endr\n"
+
+// B = max(B, T, H) after an odd step.
+#define MAXSS_BANK_MAX3                                                           \
   ".irp j, " MAXSS_IRP16 "\n"                                                     \
   "v_pk_minimum3_f16 v[224+\\j], v[224+\\j], v[208+\\j], v[192+\\j]\n"            \
-  ".endr\n"                                                                       \
+  ".endr\n"
+
+// Step t of a block with no N: the index switches on at even steps (the code
+// word itself at steps 0, 4, 8, 12), changes at odd steps, and switches off
+// before the minimum3.
+#define MAXSS_BANK_FAST_STEP                                                      \
+  MAXSS_BANK_CW                                                                   \
+  ".if (\\t & 3) == 0\n"                                                          \
+  MAXSS_SEL4("s_set_gpr_idx_on ", ", gpr_idx(SRC0)")                              \
+  ".else\n"                                                                       \
+  MAXSS_SEL4("s_lshr_b32 %[sc], ", ", 8*(\\t&3)")                                 \
+  ".if (\\t & 1) == 0\n"                                                          \
+  "s_set_gpr_idx_on %[sc], gpr_idx(SRC0)\n"                                       \
+  ".else\n"                                                                       \
+  "s_set_gpr_idx_idx %[sc]\n"                                                     \
+  ".endif\n"                                                                      \
+  ".endif\n"                                                                      \
+  MAXSS_BANK_ADDS                                                                 \
+  ".if (\\t & 1) == 1\n"                                                          \
+  "s_set_gpr_idx_off\n" MAXSS_BANK_MAX3                                           \
   ".endif\n"
 
-// The out-of-line N steps of MAXSS_BANK_STEP.
+// Step t of a block with an N (or of the tail): code byte, N branch.
+#define MAXSS_BANK_SLOW_STEP(L)                                                   \
+  MAXSS_BANK_CW                                                                   \
+  MAXSS_SEL4("s_bfe_u32 %[sc], ", ", (8*(\\t&3))|0x80000")                        \
+  "s_cmp_eq_u32 %[sc], 0x40\n"                                                    \
+  "s_cbranch_scc1 .L" L "N%=_\\t\n"                                               \
+  "s_set_gpr_idx_on %[sc], gpr_idx(SRC0)\n"                                       \
+  MAXSS_BANK_ADDS                                                                 \
+  "s_set_gpr_idx_off\n"                                                           \
+  ".L" L "R%=_\\t:\n"                                                             \
+  ".if (\\t & 1) == 1\n" MAXSS_BANK_MAX3 ".endif\n"
+
+// The out-of-line N steps of MAXSS_BANK_SLOW_STEP: add (X, X).
 #define MAXSS_BANK_NSTEP(L)                                                       \
   ".L" L "N%=_\\t:\n"                                                             \
   ".irp j, " MAXSS_IRP16 "\n"                                                     \
@@ -474,44 +508,56 @@ __device__ inline void bank_init(uint32_t la, const uint32_t (&pl)[4], const uin
 // FIRST+15 (the next block's in the other 16).  The 16 words that replace
 // the current ones (LDS byte address la) are staged at the start and fill
 // slot FIRST+s four steps after its last use (slots 12..15 at the end).
-// c0, c1: the 4-bit codes of the 16 read positions.
+// c0..c3: the code bytes of the 16 read positions.  A block without N
+// (every code byte has bit 4 set) takes the fast step sequence.
+#define MAXSS_BANK_RELOAD                                                         \
+  ".if \\t == 4\n"                                                                \
+  "s_waitcnt lgkmcnt(0)\n"                                                        \
+  ".endif\n"                                                                      \
+  ".if \\t >= 4\n" MAXSS_BANK_FILL("%[f]+\\t-4", "\\t-4") ".endif\n"
+
 template <int FIRST>
-__device__ inline void bank_block(uint32_t c0, uint32_t c1, uint32_t la,
-                                  const uint32_t (&pl)[4], const uint32_t (&ph)[4],
-                                  uint32_t xx) {
+__device__ inline void bank_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                  uint32_t la, const uint32_t (&pl)[4],
+                                  const uint32_t (&ph)[4], uint32_t xx) {
   uint32_t sc, sm;
   asm volatile(
       "s_mov_b32 %[sm], m0\n"
       ".irp i, 0,2,4,6,8,10,12,14\n"
       "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:\\i offset1:\\i+1\n"
       ".endr\n"
-      ".irp t, " MAXSS_IRP16 "\n"
-      MAXSS_BANK_STEP("b")
-      ".if \\t == 4\n"
-      "s_waitcnt lgkmcnt(0)\n"
-      ".endif\n"
-      ".if \\t >= 4\n" MAXSS_BANK_FILL("%[f]+\\t-4", "\\t-4") ".endif\n"
-      ".endr\n"
+      "s_and_b32 %[sc], %[c0], %[c1]\n"
+      "s_and_b32 %[sc], %[sc], %[c2]\n"
+      "s_and_b32 %[sc], %[sc], %[c3]\n"
+      "s_and_b32 %[sc], %[sc], 0x10101010\n"
+      "s_cmp_eq_u32 %[sc], 0x10101010\n"
+      "s_cbranch_scc0 .LbS%=\n"
+      ".irp t, " MAXSS_IRP16 "\n" MAXSS_BANK_FAST_STEP MAXSS_BANK_RELOAD ".endr\n"
+      ".irp s, 12,13,14,15\n" MAXSS_BANK_FILL("%[f]+\\s", "\\s") ".endr\n"
+      "s_branch .LbE%=\n"
+      ".LbS%=:\n"
+      ".irp t, " MAXSS_IRP16 "\n" MAXSS_BANK_SLOW_STEP("b") MAXSS_BANK_RELOAD ".endr\n"
       ".irp s, 12,13,14,15\n" MAXSS_BANK_FILL("%[f]+\\s", "\\s") ".endr\n"
       "s_branch .LbE%=\n"
       ".irp t, " MAXSS_IRP16 "\n" MAXSS_BANK_NSTEP("b") ".endr\n"
       ".LbE%=:\n"
       "s_mov_b32 m0, %[sm]\n"
       : [sc] "=&s"(sc), [sm] "=&s"(sm)
-      : [c0] "s"(c0), [c1] "s"(c1), [la] "v"(la), [xx] "s"(xx), [f] "n"(FIRST),
-        MAXSS_BANK_POOLS
+      : [c0] "s"(c0), [c1] "s"(c1), [c2] "s"(c2), [c3] "s"(c3), [la] "v"(la), [xx] "s"(xx),
+        [f] "n"(FIRST), MAXSS_BANK_POOLS
       : "scc", "memory", MAXSS_BANK_CLOBBERS);
 }
 
 // The last rem (1..15) steps of the read, window in slots FIRST.. as in
 // bank_block, no reloads.  An even last step folds T into B on exit.
 template <int FIRST>
-__device__ inline void bank_tail(uint32_t c0, uint32_t c1, uint32_t rem, uint32_t xx) {
+__device__ inline void bank_tail(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                 uint32_t rem, uint32_t xx) {
   uint32_t sc, sm;
   asm volatile(
       "s_mov_b32 %[sm], m0\n"
       ".irp t, 0,1,2,3,4,5,6,7,8,9,10,11,12,13,14\n"
-      MAXSS_BANK_STEP("t")
+      MAXSS_BANK_SLOW_STEP("t")
       "s_cmp_eq_u32 %[rem], \\t+1\n"
       ".if (\\t & 1) == 0\n"
       "s_cbranch_scc1 .LtX%=\n"
@@ -528,7 +574,8 @@ __device__ inline void bank_tail(uint32_t c0, uint32_t c1, uint32_t rem, uint32_
       ".LtE%=:\n"
       "s_mov_b32 m0, %[sm]\n"
       : [sc] "=&s"(sc), [sm] "=&s"(sm)
-      : [c0] "s"(c0), [c1] "s"(c1), [rem] "s"(rem), [xx] "s"(xx), [f] "n"(FIRST)
+      : [c0] "s"(c0), [c1] "s"(c1), [c2] "s"(c2), [c3] "s"(c3), [rem] "s"(rem), [xx] "s"(xx),
+        [f] "n"(FIRST)
       : "scc", MAXSS_BANK_CLOBBERS);
 }
 
@@ -550,8 +597,8 @@ __device__ inline void bank_extract(s16x2 (&B)[16]) {
 }
 
 // Kadane over one read strand of length m for this lane's 16 offset pairs
-// with the register banks (same window layout and code words as
-// kadane_pairs<16, ...>).  xx: the pair (X, X).
+// with the register banks (same window layout as kadane_pairs<16, ...>).  lc:
+// the strand's code bytes (four per word).  xx: the pair (X, X).
 __device__ inline void kadane_pairs_bank(const uint32_t* __restrict__ lds, uint32_t lane,
                                          const uint32_t* __restrict__ lc, uint32_t m,
                                          uint64_t xpool, uint64_t dpool, uint32_t xx,
@@ -567,36 +614,43 @@ __device__ inline void kadane_pairs_bank(const uint32_t* __restrict__ lds, uint3
   const uint32_t la = lds_byte_addr(lds + lane * (NP + 1));
   bank_init(la, pl, ph);
   const uint32_t mfull = m / NP * NP;
-  // codes of the next block are read before the current block's asm, so the
+  // the next block's codes are read before the current block's asm, so the
   // LDS latency hides behind it
-  uint32_t n0 = lc[0], n1 = lc[1];
+  uint32_t n[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) n[i] = lc[i];
+  uint32_t c[4];
   uint32_t kb = 0, pb = 0;
   for (; kb + 2 * NP <= mfull; kb += 2 * NP, pb += 2 * (NP + 1)) {
-    uint32_t c0 = __builtin_amdgcn_readfirstlane(n0), c1 = __builtin_amdgcn_readfirstlane(n1);
-    n0 = lc[(kb + NP) / 8];
-    n1 = lc[(kb + NP) / 8 + 1];
-    bank_block<0>(c0, c1, la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
-    c0 = __builtin_amdgcn_readfirstlane(n0);
-    c1 = __builtin_amdgcn_readfirstlane(n1);
-    n0 = lc[(kb + 2 * NP) / 8];
-    n1 = lc[(kb + 2 * NP) / 8 + 1];
-    bank_block<16>(c0, c1, la + 4u * (pb + 3 * (NP + 1)), pl, ph, xx);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      c[i] = __builtin_amdgcn_readfirstlane(n[i]);
+      n[i] = lc[(kb + NP) / 4 + i];
+    }
+    bank_block<0>(c[0], c[1], c[2], c[3], la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      c[i] = __builtin_amdgcn_readfirstlane(n[i]);
+      n[i] = lc[(kb + 2 * NP) / 4 + i];
+    }
+    bank_block<16>(c[0], c[1], c[2], c[3], la + 4u * (pb + 3 * (NP + 1)), pl, ph, xx);
   }
   bool odd = false;
   if (kb < mfull) {
-    const uint32_t c0 = __builtin_amdgcn_readfirstlane(n0),
-                   c1 = __builtin_amdgcn_readfirstlane(n1);
-    n0 = lc[(kb + NP) / 8];
-    n1 = lc[(kb + NP) / 8 + 1];
-    bank_block<0>(c0, c1, la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      c[i] = __builtin_amdgcn_readfirstlane(n[i]);
+      n[i] = lc[(kb + NP) / 4 + i];
+    }
+    bank_block<0>(c[0], c[1], c[2], c[3], la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
     odd = true;
   }
   const uint32_t rem = m - mfull;
   if (rem) {
-    const uint32_t c0 = __builtin_amdgcn_readfirstlane(n0),
-                   c1 = __builtin_amdgcn_readfirstlane(n1);
-    if (odd) bank_tail<16>(c0, c1, rem, xx);
-    else bank_tail<0>(c0, c1, rem, xx);
+#pragma unroll
+    for (int i = 0; i < 4; i++) c[i] = __builtin_amdgcn_readfirstlane(n[i]);
+    if (odd) bank_tail<16>(c[0], c[1], c[2], c[3], rem, xx);
+    else bank_tail<0>(c[0], c[1], c[2], c[3], rem, xx);
   }
   bank_extract(B);
 }
@@ -650,7 +704,17 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
       const uint32_t r = idx / (2 * a.cw), rem = idx - r * 2 * a.cw;
       const uint32_t s = rem / a.cw, wd = rem - s * a.cw;
       const uint32_t rid = a.order[rbase + r];
-      lcodes[idx] = wd < a.cwg ? a.sel4[((uint64_t)rid * 2 + s) * a.cwg + wd] : 0x44444444u;
+      if constexpr (BANK) {
+        // code bytes 16c, four positions per word (two LDS words per code word)
+        const uint32_t nw = wd >> 1;
+        const uint32_t v =
+            nw < a.cwg ? a.sel4[((uint64_t)rid * 2 + s) * a.cwg + nw] : 0x44444444u;
+        const uint32_t h = (wd & 1) ? v >> 16 : v & 0xFFFFu;
+        lcodes[idx] = ((h & 0xFu) << 4) | ((h & 0xF0u) << 8) | ((h & 0xF00u) << 12) |
+                      ((h & 0xF000u) << 16);
+      } else {
+        lcodes[idx] = wd < a.cwg ? a.sel4[((uint64_t)rid * 2 + s) * a.cwg + wd] : 0x44444444u;
+      }
     }
     if constexpr (QS) {
       // position-score pairs of the scanned positions, two per word; strand
@@ -1045,6 +1109,7 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
   t.cw = mstride / 8 + (uint32_t)t.NP / 8 + 1;
   t.qs = qual_mode(ix);
   t.wide = score_bound(ix) > kNarrowScoreMax;
+  if (t.NP == 16 && !t.qs && !t.wide) t.cw *= 2;  // register banks: code bytes
   t.cq = t.qs ? (mstride / scan_step(ix) + 1) / 2 + 1 : 0u;
   const size_t win_bytes = (size_t)t.win_slots * 4u;
   const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
