@@ -65,10 +65,6 @@ uint8_t host_code(char c);
 // base is scored (MAXSS_FAST), else 1.
 inline uint32_t scan_step(const Index* ix) { return (ix->p.flags & MAXSS_FAST) ? 2u : 1u; }
 
-// Window start offsets of one parity class in a fragment (F / step; F is a
-// multiple of 16).
-inline uint32_t parity_offsets(const Index* ix) { return ix->F / scan_step(ix); }
-
 // Padded read-profile stride (positions per read per strand) for an index.
 inline uint32_t read_stride(const Index* ix) { return (ix->p.max_read_len + 63u) & ~63u; }
 

@@ -78,8 +78,8 @@ static std::vector<TileOverride> tile_candidates(const Index* ix) {
   const uint32_t rs[3] = {8, 16, 32};
   const uint32_t rounds[3] = {4, 8, 16};
   for (int np : nps) {
-    const uint32_t Fp = parity_offsets(ix);
-    if (128u * (uint32_t)np > (Fp > 1024u ? Fp : 1024u)) continue;  // mostly idle lanes
+    const uint32_t F = ix->F;  // a segment covers 128*np window offsets of a fragment
+    if (128u * (uint32_t)np > (F > 1024u ? F : 1024u)) continue;  // mostly idle lanes
     for (uint32_t R : rs)
       for (uint32_t rd : rounds) c.push_back(TileOverride{np, R, rd});
   }

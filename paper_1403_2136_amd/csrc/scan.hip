@@ -737,26 +737,31 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
     for (uint32_t fi = f0; fi < f1; fi++) {
       const uint32_t f = clist ? (uint32_t)clist[fi] : fi;
       int fv = -1;  // lane r: value of fragment f for read r
-      // A segment holds S offsets of each parity class: with step 1 the
-      // offsets seg*S + x, with step 2 the offsets seg*2S + par + 2x.  The
-      // window word x of a parity is the genome at base + step*x, so one
-      // Kadane step still advances the window by one LDS word.
-      for (uint32_t sp = 0; sp < a.nseg * a.step; sp++) {
-        const uint32_t seg = sp / a.step, par = sp - seg * a.step;
-        const uint64_t base = (uint64_t)f * a.F + (uint64_t)seg * S * a.step + par;
+      // A segment holds the S window offsets seg*S .. seg*S+S-1.  With step 1
+      // the pair of x (x < HALF) is (seg*S + x, seg*S + HALF + x); with step 2
+      // (every other read base scored) it is (seg*S + 2x, seg*S + 2x + 1), the
+      // two parities side by side.  Window word w holds the genome at
+      // base + step*w and at HALF (step 1) or 1 (step 2) further, so one Kadane
+      // step advances the window by one LDS word either way.
+      for (uint32_t seg = 0; seg < a.nseg; seg++) {
+        const uint64_t base = (uint64_t)f * a.F + (uint64_t)seg * S;
+        const uint32_t hi_off = a.step == 1 ? HALF : 1u;
         __syncthreads();  // previous segment's readers are done with LDS
         for (uint32_t wd = lane; wd < nwords; wd += 64) {
           const uint64_t P = base + (uint64_t)a.step * wd;
           const uint32_t c0 = genome_code(a.g2, a.nmask, a.Lpad, P);
-          const uint32_t c1 = genome_code(a.g2, a.nmask, a.Lpad, P + (uint64_t)a.step * HALF);
+          const uint32_t c1 = genome_code(a.g2, a.nmask, a.Lpad, P + hi_off);
           lds[phys<NP>(wd)] = sel16(c0) | (sel16(c1) << 16);
         }
         __syncthreads();
-        // offsets of this parity left in the fragment from the segment start
-        const int left = ((int)a.F - (int)(seg * S * a.step + par) + (int)a.step - 1) / (int)a.step;
+        // window offsets left in the fragment from the segment start, and the
+        // pairs whose low / high offset is one of them
+        const int left = (int)a.F - (int)(seg * S);
         const bool partial_seg = left < (int)S;
-        const int lo_cnt = min(max(left - (int)(lane * NP), 0), NP);
-        const int hi_cnt = min(max(left - (int)HALF - (int)(lane * NP), 0), NP);
+        const int left_lo = a.step == 1 ? left : (left + 1) / 2;
+        const int left_hi = a.step == 1 ? left - (int)HALF : left / 2;
+        const int lo_cnt = min(max(left_lo - (int)(lane * NP), 0), NP);
+        const int hi_cnt = min(max(left_hi - (int)(lane * NP), 0), NP);
         for (uint32_t r = 0; r < rcount; r++) {
           const uint32_t m = __builtin_amdgcn_readlane(my_len, r);
           if (m == 0) continue;
@@ -1085,7 +1090,7 @@ static constexpr uint64_t kNarrowScoreMax = 31744;
 static constexpr size_t kScanLdsBudget = 40 * 1024;
 
 static int np_for(const Index* ix, const TileOverride* force) {
-  const uint32_t F = parity_offsets(ix);
+  const uint32_t F = ix->F;
   if (force && (force->NP == 8 || force->NP == 16 || force->NP == 32)) return force->NP;
   // plain scores within the narrow bound: NP = 16 runs the register-bank kernel
   if (F % 2048 == 0 && !qual_mode(ix) && score_bound(ix) <= kNarrowScoreMax) return 16;
@@ -1104,7 +1109,7 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
   Tiles t{};
   t.NP = np_for(ix, force);
   const uint32_t S = 128u * t.NP;
-  t.nseg = (parity_offsets(ix) + S - 1) / S;
+  t.nseg = (ix->F + S - 1) / S;
   t.win_slots = win_slots_for(t.NP, mstride);
   t.cw = mstride / 8 + (uint32_t)t.NP / 8 + 1;
   t.qs = qual_mode(ix);

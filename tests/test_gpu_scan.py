@@ -137,9 +137,30 @@ def test_exact_repeats_ties():
     assert (got["score"][:, 0] == 60).all()
 
 
-def test_one_strand_flag():
-    got, ref = _edge_case(30_000, 1024, [90] * 20, seed=13, flags=mx.MAXSS_ONE_STRAND)
+@pytest.mark.parametrize("F", [1024, 2048])
+def test_one_strand_flag(F):
+    got, ref = _edge_case(30_000, F, [90] * 20, seed=13, flags=mx.MAXSS_ONE_STRAND)
     assert_same(got, ref, "one strand")
+
+
+def test_bank_kernel_n_in_every_block_position():
+    # reads with N at each step of a 16-step block, in full blocks and in the
+    # m % 16 tail, and reads that are N up to one base (register-bank path)
+    g = gen.uniform_genome(40_000, 41)
+    src = g.seq[3000:3000 + 90].tobytes()
+    reads = []
+    for p in list(range(0, 48)) + [80, 85, 89]:
+        r = bytearray(src)
+        r[p] = ord("N")
+        reads.append(bytes(r))
+    reads += [b"N" * 89 + src[:1], src[:1] + b"N" * 40, b"N" * 16 + src[16:64]]
+    s, off = csr(reads)
+    ix = mx.Index(g.seq, 2048, 90)
+    assert ix.kernel_info()[1] == mx.MAXSS_KERNEL_REGISTER_BANK
+    got = ix.scan(s, off)
+    ref = oracle.scan(g.seq, 2048, s, off, nthreads=8)
+    ix.close()
+    assert_same(got, ref, "N positions")
 
 
 @pytest.mark.parametrize("F", [1024, 2048])
