@@ -488,9 +488,9 @@ __device__ inline void bank_init(uint32_t la, const uint32_t (&pl)[4], const uin
       ".irp i, 0,2,4,6,8,10,12,14\n"
       "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:\\i offset1:\\i+1\n"
       ".endr\n"
-      ".irp j, " MAXSS_IRP16 "\n"
-      "v_mov_b32 v[192+\\j], 0x80008000\n"
-      "v_mov_b32 v[224+\\j], 0x80008000\n"
+      ".irp j, 0,2,4,6,8,10,12,14\n"
+      "v_mov_b64 v[192+\\j:193+\\j], %[zero]\n"
+      "v_mov_b64 v[224+\\j:225+\\j], %[zero]\n"
       ".endr\n"
       "s_waitcnt lgkmcnt(0)\n"
       ".irp s, " MAXSS_IRP16 "\n" MAXSS_BANK_FILL("\\s", "\\s") ".endr\n"
@@ -500,7 +500,7 @@ __device__ inline void bank_init(uint32_t la, const uint32_t (&pl)[4], const uin
       "s_waitcnt lgkmcnt(0)\n"
       ".irp s, " MAXSS_IRP16 "\n" MAXSS_BANK_FILL("16+\\s", "\\s") ".endr\n"
       :
-      : [la] "v"(la), MAXSS_BANK_POOLS
+      : [la] "v"(la), [zero] "s"(0x8000800080008000ull), MAXSS_BANK_POOLS
       : "memory", MAXSS_BANK_CLOBBERS);
 }
 
@@ -596,13 +596,32 @@ __device__ inline void bank_extract(s16x2 (&B)[16]) {
   for (int j = 0; j < 16; j++) B[j] = __builtin_bit_cast(s16x2, o[j]);
 }
 
+// max(bm, B[0..15]) as one pair, by eight minimum3 on the biased values.
+__device__ inline uint32_t bank_fold(uint32_t bm) {
+  uint32_t r;
+  asm volatile(
+      "v_pk_minimum3_f16 v224, v224, v225, v226\n"
+      "v_pk_minimum3_f16 v227, v227, v228, v229\n"
+      "v_pk_minimum3_f16 v230, v230, v231, v232\n"
+      "v_pk_minimum3_f16 v233, v233, v234, v235\n"
+      "v_pk_minimum3_f16 v236, v236, v237, v238\n"
+      "v_pk_minimum3_f16 v224, v224, v227, v230\n"
+      "v_pk_minimum3_f16 v233, v233, v236, v239\n"
+      "s_nop 0\n"
+      "v_pk_minimum3_f16 %[r], v224, v233, %[bm]\n"
+      : [r] "=v"(r)
+      : [bm] "v"(bm)
+      : "v224", "v227", "v230", "v233", "v236");
+  return r;
+}
+
 // Kadane over one read strand of length m for this lane's 16 offset pairs
-// with the register banks (same window layout as kadane_pairs<16, ...>).  lc:
-// the strand's code bytes (four per word).  xx: the pair (X, X).
+// with the register banks (same window layout as kadane_pairs<16, ...>); the
+// per-pair maxima stay in v224..v239 (bank_extract, bank_fold).  lc: the
+// strand's code bytes (four per word).  xx: the pair (X, X).
 __device__ inline void kadane_pairs_bank(const uint32_t* __restrict__ lds, uint32_t lane,
                                          const uint32_t* __restrict__ lc, uint32_t m,
-                                         uint64_t xpool, uint64_t dpool, uint32_t xx,
-                                         s16x2 (&B)[16]) {
+                                         uint64_t xpool, uint64_t dpool, uint32_t xx) {
   constexpr uint32_t NP = 16;
   uint32_t pl[4], ph[4];
 #pragma unroll
@@ -652,7 +671,6 @@ __device__ inline void kadane_pairs_bank(const uint32_t* __restrict__ lds, uint3
     if (odd) bank_tail<16>(c[0], c[1], c[2], c[3], rem, xx);
     else bank_tail<0>(c[0], c[1], c[2], c[3], rem, xx);
   }
-  bank_extract(B);
 }
 #pragma clang diagnostic pop
 
@@ -768,12 +786,18 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
           uint32_t bm = 0x80008000u;
           for (uint32_t s = 0; s < a.nstrands; s++) {
             s16x2 B[NP];
-            if constexpr (BANK)
+            if constexpr (BANK) {
               kadane_pairs_bank(lds, lane, lcodes + (r * 2 + s) * a.cw, m, a.xpool, a.dpool,
-                                xx, B);
-            else
+                                xx);
+              if (!partial_seg) {
+                bm = bank_fold(bm);
+                continue;
+              }
+              bank_extract(B);
+            } else {
               kadane_pairs<NP, QS, WIDE>(lds, lane, lcodes + (r * 2 + s) * a.cw,
                                          lqs + (r * 2 + s) * a.cq, m, a.xpool, a.dpool, B);
+            }
             if (partial_seg) {
 #pragma unroll
               for (int j = 0; j < NP; j++) {
