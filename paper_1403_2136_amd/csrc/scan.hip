@@ -509,23 +509,29 @@ __device__ inline void bank_init(uint32_t la, const uint32_t (&pl)[4], const uin
 // the current ones (LDS byte address la) are staged at the start and fill
 // slot FIRST+s four steps after its last use (slots 12..15 at the end).
 // c0..c3: the code bytes of the 16 read positions.  A block without N
-// (every code byte has bit 4 set) takes the fast step sequence.
+// (every code byte has bit 4 set) takes the fast step sequence.  The last
+// block of a read (RELOAD false) stages nothing: the tail fills the few
+// words it still needs.
 #define MAXSS_BANK_RELOAD                                                         \
+  ".if %[rl]\n"                                                                   \
   ".if \\t == 4\n"                                                                \
   "s_waitcnt lgkmcnt(0)\n"                                                        \
   ".endif\n"                                                                      \
-  ".if \\t >= 4\n" MAXSS_BANK_FILL("%[f]+\\t-4", "\\t-4") ".endif\n"
+  ".if \\t >= 4\n" MAXSS_BANK_FILL("%[f]+\\t-4", "\\t-4") ".endif\n"             \
+  ".endif\n"
 
-template <int FIRST>
+template <int FIRST, bool RELOAD>
 __device__ inline void bank_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                   uint32_t la, const uint32_t (&pl)[4],
                                   const uint32_t (&ph)[4], uint32_t xx) {
   uint32_t sc, sm;
   asm volatile(
       "s_mov_b32 %[sm], m0\n"
+      ".if %[rl]\n"
       ".irp i, 0,2,4,6,8,10,12,14\n"
       "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:\\i offset1:\\i+1\n"
       ".endr\n"
+      ".endif\n"
       "s_and_b32 %[sc], %[c0], %[c1]\n"
       "s_and_b32 %[sc], %[sc], %[c2]\n"
       "s_and_b32 %[sc], %[sc], %[c3]\n"
@@ -533,29 +539,50 @@ __device__ inline void bank_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_
       "s_cmp_eq_u32 %[sc], 0x10101010\n"
       "s_cbranch_scc0 .LbS%=\n"
       ".irp t, " MAXSS_IRP16 "\n" MAXSS_BANK_FAST_STEP MAXSS_BANK_RELOAD ".endr\n"
+      ".if %[rl]\n"
       ".irp s, 12,13,14,15\n" MAXSS_BANK_FILL("%[f]+\\s", "\\s") ".endr\n"
+      ".endif\n"
       "s_branch .LbE%=\n"
       ".LbS%=:\n"
       ".irp t, " MAXSS_IRP16 "\n" MAXSS_BANK_SLOW_STEP("b") MAXSS_BANK_RELOAD ".endr\n"
+      ".if %[rl]\n"
       ".irp s, 12,13,14,15\n" MAXSS_BANK_FILL("%[f]+\\s", "\\s") ".endr\n"
+      ".endif\n"
       "s_branch .LbE%=\n"
       ".irp t, " MAXSS_IRP16 "\n" MAXSS_BANK_NSTEP("b") ".endr\n"
       ".LbE%=:\n"
       "s_mov_b32 m0, %[sm]\n"
       : [sc] "=&s"(sc), [sm] "=&s"(sm)
       : [c0] "s"(c0), [c1] "s"(c1), [c2] "s"(c2), [c3] "s"(c3), [la] "v"(la), [xx] "s"(xx),
-        [f] "n"(FIRST), MAXSS_BANK_POOLS
+        [f] "n"(FIRST), [rl] "n"(RELOAD ? 1 : 0), MAXSS_BANK_POOLS
       : "scc", "memory", MAXSS_BANK_CLOBBERS);
 }
 
 // The last rem (1..15) steps of the read, window in slots FIRST.. as in
-// bank_block, no reloads.  An even last step folds T into B on exit.
+// bank_block.  nf words (read positions mfull+16.., LDS byte address la)
+// go into the other half first; no other reloads.  An even last step folds
+// T into B on exit.
 template <int FIRST>
 __device__ inline void bank_tail(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                 uint32_t rem, uint32_t xx) {
+                                 uint32_t rem, uint32_t xx, uint32_t nf, uint32_t la,
+                                 const uint32_t (&pl)[4], const uint32_t (&ph)[4]) {
   uint32_t sc, sm;
   asm volatile(
       "s_mov_b32 %[sm], m0\n"
+      // the first nf words of the other half (LDS byte address la), which
+      // the last block did not stage
+      "s_cmp_eq_u32 %[nf], 0\n"
+      "s_cbranch_scc1 .LtP%=\n"
+      ".irp i, 0,2,4,6,8,10,12,14\n"
+      "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:\\i offset1:\\i+1\n"
+      ".endr\n"
+      "s_waitcnt lgkmcnt(0)\n"
+      ".irp s, 0,1,2,3,4,5,6,7,8,9,10,11,12,13,14\n"
+      "s_cmp_le_u32 %[nf], \\s\n"
+      "s_cbranch_scc1 .LtP%=\n"
+      MAXSS_BANK_FILL("%[g]+\\s", "\\s")
+      ".endr\n"
+      ".LtP%=:\n"
       ".irp t, 0,1,2,3,4,5,6,7,8,9,10,11,12,13,14\n"
       MAXSS_BANK_SLOW_STEP("t")
       "s_cmp_eq_u32 %[rem], \\t+1\n"
@@ -575,8 +602,8 @@ __device__ inline void bank_tail(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t
       "s_mov_b32 m0, %[sm]\n"
       : [sc] "=&s"(sc), [sm] "=&s"(sm)
       : [c0] "s"(c0), [c1] "s"(c1), [c2] "s"(c2), [c3] "s"(c3), [rem] "s"(rem), [xx] "s"(xx),
-        [f] "n"(FIRST)
-      : "scc", MAXSS_BANK_CLOBBERS);
+        [f] "n"(FIRST), [g] "n"(FIRST ^ 16), [nf] "s"(nf), [la] "v"(la), MAXSS_BANK_POOLS
+      : "scc", "memory", MAXSS_BANK_CLOBBERS);
 }
 
 __device__ inline void bank_extract(s16x2 (&B)[16]) {
@@ -632,46 +659,56 @@ __device__ inline void kadane_pairs_bank(const uint32_t* __restrict__ lds, uint3
   }
   const uint32_t la = lds_byte_addr(lds + lane * (NP + 1));
   bank_init(la, pl, ph);
-  const uint32_t mfull = m / NP * NP;
+  const uint32_t mfull = m / NP * NP, nblk = m / NP;
   // the next block's codes are read before the current block's asm, so the
   // LDS latency hides behind it
   uint32_t n[4];
 #pragma unroll
   for (int i = 0; i < 4; i++) n[i] = lc[i];
   uint32_t c[4];
-  uint32_t kb = 0, pb = 0;
-  for (; kb + 2 * NP <= mfull; kb += 2 * NP, pb += 2 * (NP + 1)) {
+  // block b covers read positions 16b..16b+15; pb: padded LDS index of word
+  // 16b.  Every block but the last stages the 16 words two blocks ahead.
+  uint32_t b = 0, pb = 0;
+  for (; b + 2 <= nblk; b += 2, pb += 2 * (NP + 1)) {
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       c[i] = __builtin_amdgcn_readfirstlane(n[i]);
-      n[i] = lc[(kb + NP) / 4 + i];
+      n[i] = lc[(b + 1) * (NP / 4) + i];
     }
-    bank_block<0>(c[0], c[1], c[2], c[3], la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
+    bank_block<0, true>(c[0], c[1], c[2], c[3], la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       c[i] = __builtin_amdgcn_readfirstlane(n[i]);
-      n[i] = lc[(kb + 2 * NP) / 4 + i];
+      n[i] = lc[(b + 2) * (NP / 4) + i];
     }
-    bank_block<16>(c[0], c[1], c[2], c[3], la + 4u * (pb + 3 * (NP + 1)), pl, ph, xx);
+    if (b + 2 < nblk)
+      bank_block<16, true>(c[0], c[1], c[2], c[3], la + 4u * (pb + 3 * (NP + 1)), pl, ph, xx);
+    else
+      bank_block<16, false>(c[0], c[1], c[2], c[3], 0u, pl, ph, xx);
   }
   bool odd = false;
-  if (kb < mfull) {
+  if (b < nblk) {
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       c[i] = __builtin_amdgcn_readfirstlane(n[i]);
-      n[i] = lc[(kb + NP) / 4 + i];
+      n[i] = lc[(b + 1) * (NP / 4) + i];
     }
-    bank_block<0>(c[0], c[1], c[2], c[3], la + 4u * (pb + 2 * (NP + 1)), pl, ph, xx);
+    bank_block<0, false>(c[0], c[1], c[2], c[3], 0u, pl, ph, xx);
     odd = true;
   }
   const uint32_t rem = m - mfull;
   if (rem) {
 #pragma unroll
     for (int i = 0; i < 4; i++) c[i] = __builtin_amdgcn_readfirstlane(n[i]);
-    if (odd) bank_tail<16>(c[0], c[1], c[2], c[3], rem, xx);
-    else bank_tail<0>(c[0], c[1], c[2], c[3], rem, xx);
+    // words mfull+16 .. mfull+14+rem, which the last block did not stage
+    const uint32_t nf = __builtin_amdgcn_readfirstlane((nblk > 0 && rem > 1) ? rem - 1 : 0u);
+    const uint32_t w = mfull + NP;
+    const uint32_t lt = la + 4u * (w + w / NP);
+    if (odd) bank_tail<16>(c[0], c[1], c[2], c[3], rem, xx, nf, lt, pl, ph);
+    else bank_tail<0>(c[0], c[1], c[2], c[3], rem, xx, nf, lt, pl, ph);
   }
 }
+
 #pragma clang diagnostic pop
 
 __device__ inline int wave_max_i32(int v) {
