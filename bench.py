@@ -334,6 +334,11 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
+        if batched:
+            # a chromosome-scale step takes tens of seconds: wait for it and
+            # say so (microseconds against the step)
+            torch.cuda.synchronize()
+            log("timed step %d done" % i)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     if not batched:
