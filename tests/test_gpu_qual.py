@@ -171,3 +171,22 @@ def test_quality_index_needs_qualities():
     assert_same(ix.scan(r.seq, r.offsets, qual=q),
                 oracle.scan(seq, 2048, r.seq, r.offsets, M, X, nthreads=8), "plain")
     ix.close()
+
+
+def test_quality_longest_reads():
+    # max_read_len 7168 with qual_scale 9: the window and one read's codes and
+    # position scores take about 74 KB of LDS (NP = 32), and the score bound
+    # 64512 > 31744 selects the per-step-max kernel
+    g = gen.uniform_genome(16_000, 61)
+    parts = [gen.sample_reads(g, 1, 62 + i, [m], 0.0, 0.1) for i, m in enumerate((7168, 7001))]
+    reads = [p.read(0) for p in parts]
+    quals = [gen.sample_qualities(p, 70 + i) for i, p in enumerate(parts)]
+    off = np.zeros(len(reads) + 1, np.uint64)
+    off[1:] = np.cumsum([len(x) for x in reads])
+    rs = np.frombuffer(b"".join(reads), np.uint8)
+    qq = np.concatenate(quals)
+    ref = oracle.scan(g.seq, 4096, rs, off, 1, -1, nthreads=8, quals=qq, qscale=9)
+    ix = mx.Index(g.seq, 4096, 7168, 1, -1, -2, qual_scale=9)
+    assert ix.kernel_info()[1] == mx.MAXSS_KERNEL_STEP_MAX
+    assert_same(ix.scan(rs, off, qual=qq), ref, "7168-base reads")
+    ix.close()
