@@ -11,8 +11,9 @@
 //
 // How (gfx950 design, not the paper's Fermi layout):
 //   * A wave owns 128*NP start offsets of one fragment: lane l holds NP
-//     packed pairs of offsets (l*NP + j, l*NP + j + 64*NP).  The read base of
-//     step k is wave-uniform.
+//     packed pairs of offsets (l*NP + j, l*NP + j + 64*NP), or, when every
+//     other read base is scored, (2(l*NP + j), 2(l*NP + j) + 1).  The read
+//     base of step k is wave-uniform.
 //   * The two 16-bit substitution scores of a pair come from one v_perm_b32:
 //     the selector word (from the genome, staged in LDS) picks, for each of
 //     the two genome bases, a byte of the step's 8-byte score pool and the
