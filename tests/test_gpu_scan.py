@@ -149,7 +149,9 @@ def test_bank_kernel_n_in_every_block_position():
     g = gen.uniform_genome(40_000, 41)
     src = g.seq[3000:3000 + 90].tobytes()
     reads = []
-    for p in list(range(0, 48)) + [80, 85, 89]:
+    # m = 90: blocks 0-3 stage the window ahead, block 4 (64-79) is the last
+    # block (no staging), 80-89 the tail
+    for p in list(range(0, 48)) + [64, 70, 79, 80, 85, 89]:
         r = bytearray(src)
         r[p] = ord("N")
         reads.append(bytes(r))
