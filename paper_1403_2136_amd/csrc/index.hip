@@ -360,6 +360,15 @@ extern "C" maxss_status maxss_index_genome(const char* seq, uint64_t len,
     delete ix;
     return s;
   }
+  int lds_cu = 0;
+  if ((s = check_hip(hipDeviceGetAttribute(&lds_cu,
+                                           hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                           ix->device),
+                     "hipDeviceGetAttribute"))) {
+    delete ix;
+    return s;
+  }
+  ix->lds_per_cu = lds_cu > 0 ? (size_t)lds_cu : 0;
   std::vector<uint32_t> g2(ix->Lpad / 16, 0), nm(ix->Lpad / 32, 0);
   std::vector<uint8_t> codes(ix->Lpad, kN);
   for (uint64_t i = 0; i < ix->Lpad; i++) {

@@ -30,6 +30,7 @@ struct TileOverride {
 struct Index {
   int device = 0;
   int num_cu = 0;
+  size_t lds_per_cu = 0;  // bytes of LDS per compute unit
   TileOverride tune;     // set only by maxss_autotune
   uint64_t G = 0;
   uint32_t F = 0, NF = 0;

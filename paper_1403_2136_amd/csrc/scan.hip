@@ -1180,8 +1180,14 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
   t.cq = t.qs ? (mstride / scan_step(ix) + 1) / 2 + 1 : 0u;
   const size_t win_bytes = (size_t)t.win_slots * 4u;
   const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
+  // LDS per wave: at most kScanLdsBudget, and no more than lets every wave
+  // that the kernel's registers allow stay resident on a CU
+  size_t budget = kScanLdsBudget;
+  const int reg_waves = occupancy_for(t.NP, t.qs, t.wide, 0);
+  if (ix->lds_per_cu && reg_waves > 0 && ix->lds_per_cu / (size_t)reg_waves < budget)
+    budget = ix->lds_per_cu / (size_t)reg_waves;
   uint32_t rmax = 32;
-  while (rmax > 1 && win_bytes + rmax * per_read > kScanLdsBudget) rmax /= 2;
+  while (rmax > 1 && win_bytes + rmax * per_read > budget) rmax /= 2;
   if (win_bytes + rmax * per_read > 64 * 1024 && rmax > 1) rmax = 1;
   t.R = force->R ? (force->R < rmax ? force->R : rmax) : rmax;
   t.lds = win_bytes + t.R * per_read;
