@@ -7,8 +7,8 @@ of the two winners) followed by maxss_align_top (NW of every read on its best
 fragment).  The metric is MaxSS GCUPS = (sum over reads of 2 * G * m) / step
 time / 1e9 (both strands, every genome start position).
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build measures
-one GPU (see the sharding notes in the design document).
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the benchmark
+measures one GPU (the scan shards by reads across GPUs with no collective).
 """
 from __future__ import annotations
 
@@ -258,7 +258,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the MaxSS scan shards by reads with no "
-              "collective, and this build reports the single-GPU rate (run with --gpus 1)",
+              "collective, and the benchmark reports the single-GPU rate (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -1,7 +1,7 @@
 """Float64 oracle of the learned fragment proposal -- TEST INFRASTRUCTURE ONLY.
 
 The paper has no learned component.  These functions define, plainly and in
-float64, the proposal this build adds on top of the exact scan; the GPU path
+float64, the proposal added on top of the exact scan; the GPU path
 must match them within the tolerances derived in the tests.  Only `tests/`,
 the smoke check and the benchmark's CPU-baseline leg may import this module.
 
