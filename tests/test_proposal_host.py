@@ -1,4 +1,4 @@
-"""Host-side logic of the proposal driver (no GPU): threshold choice,
+"""Host-side logic of the proposal training and evaluation loop (no GPU): threshold choice,
 recall and agreement."""
 import numpy as np
 
