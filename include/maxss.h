@@ -248,7 +248,8 @@ typedef struct {
  * shape's on the index (used by every later scan on it).  With cache_path
  * (may be NULL), a matching entry (device architecture, fragment geometry,
  * read-length and batch-size bucket) is reused without timing, and a new
- * result is appended.  Must not run concurrently with scans on the index.
+ * result is appended; an entry whose shape maxss_index_set_tiles would
+ * reject is ignored.  Must not run concurrently with scans on the index.
  * Errors: EINVAL, ETOOLONG (host sample), ENOMEM, EDEVICE. */
 maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sample, const char* cache_path,
                             maxss_tune_result* result);

@@ -35,6 +35,7 @@ struct Plan {
   // what the captured graph was recorded for
   const void* k_seq = nullptr;
   const void* k_off = nullptr;
+  const void* k_qual = nullptr;
   uint32_t k_n = 0;
   void *k_top = nullptr, *k_aln = nullptr, *k_cig = nullptr;
   hipStream_t k_st = nullptr;
@@ -171,8 +172,8 @@ extern "C" maxss_status maxss_plan_run_graph(maxss_plan* plan, const maxss_reads
   if (reads->n == 0) return MAXSS_OK;
   hipStream_t st = (hipStream_t)stream;
   const bool same = p->exec && p->k_seq == reads->seq && p->k_off == reads->offsets &&
-                    p->k_n == reads->n && p->k_top == top && p->k_aln == aln &&
-                    p->k_cig == cigar && p->k_st == st;
+                    p->k_qual == reads->qual && p->k_n == reads->n && p->k_top == top &&
+                    p->k_aln == aln && p->k_cig == cigar && p->k_st == st;
   if (!same) {
     drop_graph(p);
     if ((s = check_hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal),
@@ -193,6 +194,7 @@ extern "C" maxss_status maxss_plan_run_graph(maxss_plan* plan, const maxss_reads
     }
     p->k_seq = reads->seq;
     p->k_off = reads->offsets;
+    p->k_qual = reads->qual;
     p->k_n = reads->n;
     p->k_top = top;
     p->k_aln = aln;
@@ -253,8 +255,10 @@ extern "C" maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sa
         float best = 0, def = 0;
         const char* bar = strchr(line, '|');
         if (!bar || std::string(line, bar - line) != key) continue;
+        // a line is taken only with the shapes maxss_index_set_tiles accepts
         if (sscanf(bar + 1, " np=%d R=%u rounds=%u best_ms=%f default_ms=%f", &np, &R, &rd, &best,
-                   &def) == 5) {
+                   &def) == 5 &&
+            (np == 0 || np == 8 || np == 16 || np == 32) && R <= 64 && rd <= 1024) {
           ix->tune = TileOverride{np, R, rd};
           result->np = np;
           result->reads_per_tile = R;

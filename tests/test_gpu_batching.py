@@ -164,4 +164,13 @@ def test_autotune_parity_gate_and_cache(tmp_path):
     res2 = ix.autotune(r.seq, r.offsets, cache)
     assert res2["from_cache"] == 1 and res2["np"] == res["np"]
     assert os.path.getsize(cache) > 0
+    # an entry with the same key but a shape outside the accepted range is
+    # skipped: the shapes are timed again
+    key = open(cache).readline().split("|")[0]
+    bad = str(tmp_path / "bad.txt")
+    with open(bad, "w") as f:
+        f.write(key + "| np=7 R=500 rounds=3 best_ms=1.0 default_ms=2.0\n")
+    res3 = ix.autotune(r.seq, r.offsets, bad)
+    assert res3["from_cache"] == 0 and res3["tried"] > 0 and res3["np"] in (0, 8, 16, 32)
+    assert_same(ix.scan(r.seq, r.offsets), ref, "after a skipped cache entry")
     ix.close()

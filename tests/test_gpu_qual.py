@@ -150,6 +150,17 @@ def test_quality_plan_graph():
     exp = oracle.align_top(seq, 2048, r.seq, r.offsets, ref, 50, M, X, GAP, quals=q, qscale=QS)
     a = aln.cpu().numpy().view(mx.ALN_DTYPE)
     assert [int(x) for x in a["score"]] == [e["score"] for e in exp]
+    # the same reads with qualities in another buffer: the graph is recorded
+    # again for the new buffer, not replayed with the old one
+    q2 = gen.sample_qualities(r, 4747)
+    ref2 = oracle.scan(seq, 2048, r.seq, r.offsets, M, X, nthreads=8, quals=q2, qscale=QS)
+    assert any((ref2[f] != ref[f]).any() for f in FIELDS)
+    qd2 = torch.from_numpy(q2).cuda()
+    for rep in range(2):
+        with torch.cuda.stream(stream):
+            plan.run(s, o, top, aln, cig, stream=stream, graph=True, qual=qd2)
+        stream.synchronize()
+        assert_same(top.cpu().numpy().view(mx.TOP2_DTYPE), ref2, "new qualities %d" % rep)
     plan.close()
     ix.close()
 
