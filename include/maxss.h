@@ -385,13 +385,16 @@ maxss_status maxss_sam_header(const maxss_index* index, const char* rname, char*
  * FLAG (0, 16 for the reverse strand, 4 unmapped), RNAME, POS (ref_begin+1),
  * MAPQ, CIGAR (the extended =/X/I/D string, "*" if truncated), RNEXT "*",
  * PNEXT 0, TLEN 0, SEQ (the read on the forward genome strand: reverse
- * complement for strand 1), QUAL "*", then AS:i:<NW score>.  An unmapped read
- * has RNAME "*", POS 0, MAPQ 0, CIGAR "*" and SEQ as given (upper case); a
- * read the scan marked invalid has SEQ "*".  All pointers are host pointers:
+ * complement for strand 1), QUAL (reads->qual in the order of SEQ, reversed
+ * for strand 1; "*" when reads->qual is NULL), then AS:i:<NW score>.  An
+ * unmapped read has RNAME "*", POS 0, MAPQ 0, CIGAR "*", SEQ as given (upper
+ * case) and QUAL as given; a read the scan marked invalid has SEQ and QUAL
+ * "*".  All pointers are host pointers:
  * reads (on_device = 0), top and aln (n records), cigar (n * cigar_stride
  * bytes, NUL-terminated rows as written by maxss_align_top), mapq and mapped
  * (n bytes, from maxss_mapq).  Output as for maxss_sam_header.
- * Errors: EINVAL (NULL, device reads, bad names, cap), with *len = needed. */
+ * Errors: EINVAL (NULL, device reads, bad names, a quality outside '!'..'~',
+ * cap), with *len = needed. */
 maxss_status maxss_sam_records(const maxss_reads* reads, const maxss_top2* top,
                                const maxss_aln* aln, const char* cigar, uint64_t cigar_stride,
                                const uint8_t* mapq, const uint8_t* mapped, const char* rname,

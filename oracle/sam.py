@@ -20,10 +20,11 @@ Readings (the paper does not fix them):
   - records follow SAM v1: QNAME FLAG RNAME POS MAPQ CIGAR RNEXT PNEXT TLEN
     SEQ QUAL, tab-separated, then the tag AS:i (the NW score) for mapped
     reads.  FLAG 16 marks the reverse strand; SEQ is the read on the
-    forward genome strand (reverse-complemented for strand 1); QUAL is "*".
-    An unmapped read has FLAG 4, RNAME "*", POS 0, MAPQ 0, CIGAR "*", SEQ
-    the read as given; a read marked invalid by the scan has SEQ "*".  A
-    truncated CIGAR is written as "*".
+    forward genome strand (reverse-complemented for strand 1); QUAL is the
+    read's Phred+33 string in SEQ's order (reversed for strand 1), or "*"
+    for a read without qualities.  An unmapped read has FLAG 4, RNAME "*",
+    POS 0, MAPQ 0, CIGAR "*", SEQ and QUAL as given; a read marked invalid
+    by the scan has SEQ and QUAL "*".  A truncated CIGAR is written as "*".
 """
 from __future__ import annotations
 
@@ -59,21 +60,25 @@ def header(rname: str, G: int) -> str:
 
 
 def record(name: str, read: bytes, top, aln: dict | None, rname: str, num: int = 9,
-           den: int = 10, min_mapq: int = -1, truncated: bool = False) -> str:
+           den: int = 10, min_mapq: int = -1, truncated: bool = False,
+           qual: bytes | None = None) -> str:
     """One SAM line (with its newline) from the oracle's own results: `top`
     the read's top-2 record (oracle.scan), `aln` the dict of oracle.align_one
-    (score, strand, ref_begin, ref_end, cigar); `truncated` writes CIGAR "*"."""
+    (score, strand, ref_begin, ref_end, cigar); `truncated` writes CIGAR "*";
+    `qual` the read's Phred+33 qualities as given (None: QUAL "*")."""
     f1 = int(top["frag"][0])
     s1 = int(top["score"][0])
     s2 = int(top["score"][1]) if int(top["frag"][1]) >= 0 else -1
     if f1 == INVALID:
         return "\t".join([name, "4", "*", "0", "0", "*", "*", "0", "0", "*", "*"]) + "\n"
     if not is_mapped(s1, s2, num, den, min_mapq):
+        q = qual.decode() if qual else "*"
         return "\t".join([name, "4", "*", "0", "0", "*", "*", "0", "0", read.decode().upper(),
-                          "*"]) + "\n"
+                          q]) + "\n"
     strand = int(aln["strand"])
     seq = read.decode().upper() if strand == 0 else revcomp(read)
+    q = "*" if not qual else (qual.decode() if strand == 0 else qual.decode()[::-1])
     fields = [name, "16" if strand else "0", rname, str(int(aln["ref_begin"]) + 1),
-              str(mapq(s1, s2)), "*" if truncated else aln["cigar"], "*", "0", "0", seq, "*",
+              str(mapq(s1, s2)), "*" if truncated else aln["cigar"], "*", "0", "0", seq, q,
               "AS:i:%d" % int(aln["score"])]
     return "\t".join(fields) + "\n"

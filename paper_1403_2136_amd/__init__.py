@@ -392,11 +392,13 @@ def maxss_sam_header(handle, rname: str) -> str:
 
 def maxss_sam_records(seq, offsets, top: np.ndarray, aln: np.ndarray, cigar: np.ndarray,
                       cigar_stride: int, mapq: np.ndarray, mapped: np.ndarray, rname: str,
-                      names=None) -> str:
-    """SAM lines from host copies of the records (numpy arrays)."""
+                      names=None, qual=None) -> str:
+    """SAM lines from host copies of the records (numpy arrays); `qual`
+    (Phred+33, one per read base) fills the QUAL column."""
     s, off = _host_csr(seq, offsets)
     n = off.size - 1
-    r = Reads(s.ctypes.data, off.ctypes.data, n, 0)
+    q8 = _host_qual(qual, s)
+    r = Reads(s.ctypes.data, off.ctypes.data, n, 0, q8.ctypes.data if q8 is not None else None)
     top = np.ascontiguousarray(top)
     aln = np.ascontiguousarray(aln)
     cig = np.ascontiguousarray(cigar, dtype=np.uint8)

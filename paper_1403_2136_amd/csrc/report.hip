@@ -63,6 +63,19 @@ static void put_upper(std::string& out, const char* s, uint64_t m) {
   }
 }
 
+// QUAL of a read: the Phred+33 string as given, or reversed for a record on
+// the reverse strand (SAM stores QUAL in the order of SEQ); "*" without
+// qualities.
+static void put_qual(std::string& out, const char* q, uint64_t m, bool reverse) {
+  if (!q || m == 0) {
+    out.push_back('*');
+  } else if (reverse) {
+    for (uint64_t k = m; k-- > 0;) out.push_back(q[k]);
+  } else {
+    out.append(q, m);
+  }
+}
+
 static bool valid_name(const char* s) {
   if (!s || !*s) return false;
   for (const char* p = s; *p; p++)
@@ -125,6 +138,12 @@ extern "C" maxss_status maxss_sam_records(const maxss_reads* reads, const maxss_
     if (b < a) return fail(MAXSS_EINVAL, "offsets decrease at read %u", i);
     const char* s = reads->seq + a;
     const uint64_t m = b - a;
+    const char* q = reads->qual ? reads->qual + a : nullptr;
+    if (q)
+      for (uint64_t k = 0; k < m; k++)
+        if (q[k] < '!' || q[k] > '~')
+          return fail(MAXSS_EINVAL, "read %u: quality 0x%02x at %llu outside '!'..'~'", i,
+                      (unsigned)(unsigned char)q[k], (unsigned long long)k);
     if (names) {
       if (!valid_name(names[i])) return fail(MAXSS_EINVAL, "read name %u is not printable", i);
       out += names[i];
@@ -138,7 +157,9 @@ extern "C" maxss_status maxss_sam_records(const maxss_reads* reads, const maxss_
     if (!mapped[i]) {
       out += "\t4\t*\t0\t0\t*\t*\t0\t0\t";
       put_upper(out, s, m);
-      out += "\t*\n";
+      out += "\t";
+      put_qual(out, q, m, false);
+      out += "\n";
       continue;
     }
     const maxss_aln& al = aln[i];
@@ -155,7 +176,9 @@ extern "C" maxss_status maxss_sam_records(const maxss_reads* reads, const maxss_
     out += "\t*\t0\t0\t";
     if (al.strand) put_rc(out, s, m);
     else put_upper(out, s, m);
-    out += "\t*\tAS:i:" + std::to_string(al.score) + "\n";
+    out += "\t";
+    put_qual(out, q, m, al.strand != 0);
+    out += "\tAS:i:" + std::to_string(al.score) + "\n";
   }
   *len = out.size();
   if (!buf || cap < out.size())

@@ -82,3 +82,33 @@ def test_reverse_strand_record_shows_forward_sequence():
         same = sum(a == b for a, b in zip(seq, ref))
         assert same >= 0.9 * len(seq), (i, line)
         assert (line[1] == "16") == (int(alns[i]["strand"]) == 1)
+
+
+def test_qual_column_follows_seq():
+    """QUAL stays attached to its bases: on the reverse strand SEQ[j] is the
+    complement of read base m-1-j, so QUAL[j] is that base's quality."""
+    G = gen.uniform_genome(20_000, 15)
+    r = gen.sample_reads(G, 40, 16, [45, 80], 0.0, 0.5)
+    q = gen.sample_qualities(r, 17)
+    top = oracle.scan(G.seq, 2048, r.seq, r.offsets, nthreads=4)
+    alns = oracle.align_top(G.seq, 2048, r.seq, r.offsets, top, 100)
+    comp = {"A": "T", "C": "G", "G": "C", "T": "A", "N": "N"}
+    seen = set()
+    for i in range(r.n):
+        a, b = int(r.offsets[i]), int(r.offsets[i + 1])
+        read, qi = r.read(i).decode().upper(), q[a:b].tobytes().decode()
+        line = sam.record("q", r.read(i), top[i], alns[i], "g", qual=q[a:b].tobytes())
+        f = line.rstrip("\n").split("\t")
+        seq, qual = f[9], f[10]
+        assert len(qual) == len(seq) == b - a
+        seen.add(f[1])
+        if f[1] == "16":
+            m = len(read)
+            for j in range(m):
+                assert comp[seq[j]] == read[m - 1 - j] and qual[j] == qi[m - 1 - j], (i, j)
+        else:
+            assert seq == read and qual == qi, i
+        # without qualities the column is "*"
+        plain = sam.record("q", r.read(i), top[i], alns[i], "g")
+        assert plain.rstrip("\n").split("\t")[10] == "*"
+    assert {"0", "16"} <= seen

@@ -1,7 +1,7 @@
 """The library's SAM formatting (host code) against the oracle's, on records
 the oracle computed: the hand-derived toy records, and reads with ties,
-reverse strands, unmapped and invalid reads, custom names and the strict
-threshold.  The device MAPQ kernel is checked in the GPU tests."""
+reverse strands, unmapped and invalid reads, custom names, qualities and
+the strict threshold.  The device MAPQ kernel is checked in the GPU tests."""
 import json
 import os
 
@@ -97,3 +97,26 @@ def test_bad_names_rejected():
         mx.maxss_sam_records(b"ACGT", [0, 4], top, aln, cig, 8, z, z, "has space")
     with pytest.raises(mx.MaxssError):
         mx.maxss_sam_records(b"ACGT", [0, 4], top, aln, cig, 8, z, z, "c", names=["a\tb"])
+
+
+def test_qualities_in_qual_column_equal_oracle():
+    G = gen.uniform_genome(30_000, 31)
+    s = G.seq.copy()
+    s[20_000:21_000] = s[3_000:4_000]             # exact repeat: unmapped reads
+    G = gen.Genome(s, "rep")
+    r = gen.sample_reads(G, 50, 32, [30, 75, 120], 0.0, 0.4, indel_max=1)
+    reads = [r.read(i) for i in range(r.n)]
+    q = gen.sample_qualities(r, 33)
+    seq, off, top, alns, aln, cig = _records(G.seq, 2048, reads, 50)
+    mq, m = _mapq(top)
+    txt = mx.maxss_sam_records(seq, off, top, aln, cig, 256, mq, m, "chrQ", qual=q)
+    exp = "".join(sam.record("r%d" % i, reads[i], top[i], alns[i], "chrQ",
+                             truncated=bool(aln[i]["flags"] & 1),
+                             qual=q[int(off[i]):int(off[i + 1])].tobytes())
+                  for i in range(len(reads)))
+    assert txt == exp
+    assert m.sum() > 0 and (m == 0).sum() > 0 and (top["strand"][:, 0] == 1).any()
+    bad = q.copy()
+    bad[7] = 0x20                                 # a space is no Phred+33 quality
+    with pytest.raises(mx.MaxssError):
+        mx.maxss_sam_records(seq, off, top, aln, cig, 256, mq, m, "chrQ", qual=bad)
