@@ -192,6 +192,29 @@ def _ptr(x):
     raise TypeError(type(x))
 
 
+def _buf(x, nbytes: int, what: str, optional: bool = False):
+    """Pointer of a buffer the library reads or writes nbytes of, after
+    checking that the buffer (numpy array or torch tensor) is contiguous and
+    large enough.  A raw int address is passed through unchecked."""
+    if x is None:
+        if optional:
+            return None
+        raise ValueError("%s is required" % what)
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        have, contig = x.nbytes, x.flags.c_contiguous
+    elif hasattr(x, "data_ptr"):
+        have, contig = x.numel() * x.element_size(), x.is_contiguous()
+    else:
+        raise TypeError(type(x))
+    if not contig:
+        raise ValueError("%s must be contiguous" % what)
+    if have < nbytes:
+        raise ValueError("%s holds %d bytes, %d needed" % (what, have, nbytes))
+    return _ptr(x)
+
+
 def _stream_handle(stream):
     if stream is None:
         return None
@@ -258,7 +281,9 @@ def _host_csr(seq, offsets):
 def _reads_struct(seq, offsets, on_device: bool, qual=None) -> Reads:
     n = (offsets.numel() if hasattr(offsets, "numel") else len(offsets)) - 1
     if qual is not None and hasattr(qual, "numel") and hasattr(seq, "numel"):
-        assert qual.numel() >= seq.numel(), "one quality per read base"
+        if qual.numel() < seq.numel():
+            raise ValueError("one quality per read base (%d qualities, %d bases)"
+                             % (qual.numel(), seq.numel()))
     return Reads(_ptr(seq), _ptr(offsets), n, 1 if on_device else 0, _ptr(qual))
 
 
@@ -283,7 +308,7 @@ def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None, qual=None
         r = _reads_struct(seq, offsets, True, qual)
         if out is None:
             raise ValueError("device reads need a device `out` tensor of n*32 bytes")
-        _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), _ptr(out),
+        _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), _buf(out, 32 * r.n, "out"),
                                       _stream_handle(stream)))
         return out
     s, off = _host_csr(seq, offsets)
@@ -291,7 +316,7 @@ def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None, qual=None
     n = off.size - 1
     res = np.zeros(n, dtype=TOP2_DTYPE) if out is None else out
     r = Reads(s.ctypes.data, off.ctypes.data, n, 0, _ptr(q))
-    _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), res.ctypes.data,
+    _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), _buf(res, 32 * n, "out"),
                                   _stream_handle(stream)))
     return res
 
@@ -302,8 +327,10 @@ def maxss_align_top(handle: int, seq, offsets, top, pad: int = 100, cigar_stride
     device form fills `out` (n*32 bytes) and `cigar` (n*cigar_stride bytes)."""
     if hasattr(seq, "is_cuda") and seq.is_cuda:
         r = _reads_struct(seq, offsets, True, qual)
-        _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), _ptr(top), pad, _ptr(out),
-                                     _ptr(cigar), cigar_stride, _stream_handle(stream)))
+        _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), _buf(top, 32 * r.n, "top"), pad,
+                                     _buf(out, 32 * r.n, "out"),
+                                     _buf(cigar, cigar_stride * r.n, "cigar"), cigar_stride,
+                                     _stream_handle(stream)))
         return out, cigar
     s, off = _host_csr(seq, offsets)
     q = _host_qual(qual, s)
@@ -312,7 +339,7 @@ def maxss_align_top(handle: int, seq, offsets, top, pad: int = 100, cigar_stride
     res = np.zeros(n, dtype=ALN_DTYPE)
     cig = np.zeros(n * cigar_stride, dtype=np.uint8)
     r = Reads(s.ctypes.data, off.ctypes.data, n, 0, _ptr(q))
-    _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), top.ctypes.data, pad,
+    _check(lib().maxss_align_top(h_(handle), ctypes.byref(r), _buf(top, 32 * n, "top"), pad,
                                  res.ctypes.data, cig.ctypes.data, cigar_stride,
                                  _stream_handle(stream)))
     cigars = [decode_cigar(cig, i, cigar_stride) for i in range(n)]
@@ -330,12 +357,15 @@ def maxss_plan_free(plan: int) -> None:
 
 
 def maxss_plan_run(plan: int, seq, offsets, top, aln=None, cigar=None, stream=None,
-                   graph: bool = False, qual=None):
+                   graph: bool = False, qual=None, cigar_stride: int | None = None):
     """One step on device reads (torch tensors); `graph` replays a captured
-    HIP graph (needs a non-default stream)."""
+    HIP graph (needs a non-default stream).  With cigar_stride (the plan's),
+    `cigar` is checked to hold n rows."""
     r = _reads_struct(seq, offsets, True, qual)
     fn = lib().maxss_plan_run_graph if graph else lib().maxss_plan_run
-    _check(fn(plan, ctypes.byref(r), _ptr(top), _ptr(aln), _ptr(cigar), _stream_handle(stream)))
+    cig = _buf(cigar, (cigar_stride or 0) * r.n, "cigar", optional=True)
+    _check(fn(plan, ctypes.byref(r), _buf(top, 32 * r.n, "top"),
+              _buf(aln, 32 * r.n, "aln", optional=True), cig, _stream_handle(stream)))
 
 
 def maxss_autotune(handle, seq, offsets, cache_path: str | None = None, qual=None) -> dict:
@@ -370,8 +400,9 @@ def maxss_mapq(top, n: int, mapq, mapped=None, ratio_num: int = 9, ratio_den: in
                min_mapq: int = -1, stream=None) -> None:
     """Mapping quality of n top-2 records (device tensors: top n*32 bytes,
     mapq and mapped n bytes each)."""
-    _check(lib().maxss_mapq(_ptr(top), n, ratio_num, ratio_den, min_mapq, _ptr(mapq),
-                            _ptr(mapped), _stream_handle(stream)))
+    _check(lib().maxss_mapq(_buf(top, 32 * n, "top"), n, ratio_num, ratio_den, min_mapq,
+                            _buf(mapq, n, "mapq"), _buf(mapped, n, "mapped", optional=True),
+                            _stream_handle(stream)))
 
 
 def _two_pass(call) -> str:
@@ -404,12 +435,16 @@ def maxss_sam_records(seq, offsets, top: np.ndarray, aln: np.ndarray, cigar: np.
     cig = np.ascontiguousarray(cigar, dtype=np.uint8)
     q = np.ascontiguousarray(mapq, dtype=np.uint8)
     mp = np.ascontiguousarray(mapped, dtype=np.uint8)
-    assert top.size >= n and aln.size >= n and q.size >= n and mp.size >= n
-    assert cig.size >= n * cigar_stride
+    if min(top.size, aln.size, q.size, mp.size) < n:
+        raise ValueError("top, aln, mapq and mapped need one entry per read (%d reads)" % n)
+    if cig.size < n * cigar_stride:
+        raise ValueError("cigar holds %d bytes, %d reads x stride %d needed"
+                         % (cig.size, n, cigar_stride))
     nm = None
     if names is not None:
         enc = [x.encode() for x in names]
-        assert len(enc) >= n
+        if len(enc) < n:
+            raise ValueError("%d names for %d reads" % (len(enc), n))
         nm = (ctypes.c_char_p * len(enc))(*enc)
     rn = rname.encode()
     return _two_pass(lambda b, cap, ln: lib().maxss_sam_records(
@@ -440,7 +475,8 @@ class Plan:
         self.capacity, self.pad, self.cigar_stride = capacity, pad, cigar_stride
 
     def run(self, seq, offsets, top, aln=None, cigar=None, stream=None, graph=False, qual=None):
-        maxss_plan_run(self.handle, seq, offsets, top, aln, cigar, stream, graph, qual)
+        maxss_plan_run(self.handle, seq, offsets, top, aln, cigar, stream, graph, qual,
+                       self.cigar_stride)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -479,26 +515,34 @@ class Model:
 
     def scores(self, index, seq, offsets, out, stream=None):
         r = _reads_struct(seq, offsets, True)
-        _check(lib().maxss_proposal_scores(h_(index), self.handle, ctypes.byref(r), _ptr(out),
+        nf = maxss_index_info(h_(index))[1]
+        _check(lib().maxss_proposal_scores(h_(index), self.handle, ctypes.byref(r),
+                                           _buf(out, 4 * r.n * nf, "scores"),
                                            _stream_handle(stream)))
 
     def candidates(self, index, seq, offsets, K, margin, cand, margins, fell_back, stream=None):
         r = _reads_struct(seq, offsets, True)
         _check(lib().maxss_proposal_candidates(h_(index), self.handle, ctypes.byref(r), K,
-                                               margin, _ptr(cand), _ptr(margins), _ptr(fell_back),
+                                               margin, _buf(cand, 4 * r.n * K, "cand"),
+                                               _buf(margins, 4 * r.n, "margins"),
+                                               _buf(fell_back, r.n, "fell_back"),
                                                _stream_handle(stream)))
 
     def scan(self, index, seq, offsets, K, margin, out, fell_back=None, stream=None, qual=None):
         r = _reads_struct(seq, offsets, True, qual)
         _check(lib().maxss_scan_reads_proposed(h_(index), self.handle, ctypes.byref(r), K, margin,
-                                               _ptr(out), _ptr(fell_back),
+                                               _buf(out, 32 * r.n, "out"),
+                                               _buf(fell_back, r.n, "fell_back", optional=True),
                                                _stream_handle(stream)))
 
     def train_step(self, index, seq, offsets, cand, strand, lr, loss=None, grad=None,
                    stream=None):
         r = _reads_struct(seq, offsets, True)
-        _check(lib().maxss_model_train_step(self.handle, h_(index), ctypes.byref(r), _ptr(cand),
-                                            _ptr(strand), lr, _ptr(loss), _ptr(grad),
+        _check(lib().maxss_model_train_step(self.handle, h_(index), ctypes.byref(r),
+                                            _buf(cand, 4 * 64 * r.n, "cand"),
+                                            _buf(strand, r.n, "strand"), lr,
+                                            _buf(loss, 4, "loss", optional=True),
+                                            _buf(grad, 4 * MLP_PARAMS, "grad", optional=True),
                                             _stream_handle(stream)))
 
     def close(self):
@@ -515,8 +559,12 @@ class Model:
 
 def maxss_profiles(index, seq=None, offsets=None, read_prof=None, frag_prof=None, stream=None):
     r = _reads_struct(seq, offsets, True) if seq is not None else None
+    nr = r.n if r is not None else 0
+    nf = maxss_index_info(h_(index))[1]
     _check(lib().maxss_profiles(h_(index), ctypes.byref(r) if r is not None else None,
-                                _ptr(read_prof), _ptr(frag_prof), _stream_handle(stream)))
+                                _buf(read_prof, 4 * 2 * 256 * nr, "read_prof", optional=True),
+                                _buf(frag_prof, 4 * 256 * nf, "frag_prof", optional=True),
+                                _stream_handle(stream)))
 
 
 class Index:
