@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK = 0
 ONE_STRAND = 1
 FAST = 2
+EXCL_ADJ = 4   # the second-best fragment is never a neighbour of the best
 NW_FIT = 0
 NW_GLOBAL = 1
 

@@ -49,6 +49,7 @@
 
 #define OR_ONE_STRAND 1u  /* scan the read as given only */
 #define OR_FAST 2u        /* MaxSSmap_fast: score every other read base */
+#define OR_EXCL_ADJ 4u    /* top2 skips the fragments next to top1 */
 
 /* Output record of the scan: 32 bytes, little-endian, no implicit padding. */
 typedef struct {
@@ -214,14 +215,18 @@ static void fragment_values(const char* q_fwd, const char* q_rc, uint32_t m,
 }
 
 /* Top-2 over fragments: the highest value, smallest id on ties; top2 is the
- * same rule over the fragments other than top1. */
+ * same rule over the fragments other than top1, and with excl_adj also other
+ * than top1 - 1 and top1 + 1 (a read whose alignment crosses a junction, an
+ * indel near it for instance, also scores in the neighbouring fragment; that
+ * is the same locus, not a second one). */
 static void top_two(const int32_t* v, const int32_t* s, const int32_t* o, uint32_t NF,
-                    oracle_top2* r) {
+                    int excl_adj, oracle_top2* r) {
   int32_t f1 = -1, f2 = -1;
   for (uint32_t f = 0; f < NF; f++)
     if (f1 < 0 || v[f] > v[f1]) f1 = (int32_t)f;
   for (uint32_t f = 0; f < NF; f++) {
     if ((int32_t)f == f1) continue;
+    if (excl_adj && ((int32_t)f == f1 - 1 || (int32_t)f == f1 + 1)) continue;
     if (f2 < 0 || v[f] > v[f2]) f2 = (int32_t)f;
   }
   memset(r, 0, sizeof(*r));
@@ -238,6 +243,7 @@ typedef struct {
   const char* reads; const uint64_t* offsets; uint32_t n;
   int32_t M, X; int one_strand; uint32_t step;
   const char* quals; int32_t qscale; /* optional Phred+33 qualities (CSR as reads) */
+  int excl_adj;
   int tid, nthreads;
   oracle_top2* out;
   int32_t* all_v; /* optional n x NF matrix of fragment values */
@@ -279,7 +285,7 @@ static void* scan_worker(void* arg) {
     fragment_values(q, rc, m, J->g, J->G, J->F, J->NF, J->M, J->X, J->one_strand, J->step,
                     (const int32_t* const*)sm, (const int32_t* const*)sx, v, s, o);
     for (int t = 0; t < 2; t++) { free(sm[t]); free(sx[t]); }
-    top_two(v, s, o, J->NF, &J->out[i]);
+    top_two(v, s, o, J->NF, J->excl_adj, &J->out[i]);
     if (J->all_v) memcpy(J->all_v + (uint64_t)i * J->NF, v, sizeof(int32_t) * J->NF);
     free(q); free(rc);
   }
@@ -289,7 +295,8 @@ static void* scan_worker(void* arg) {
 
 /* Full scan: top-2 record per read.  reads is a CSR concatenation (offsets has
  * n+1 entries).  all_v (may be NULL) receives the n x NF fragment values.
- * flags: OR_ONE_STRAND, OR_FAST (every other read base, per strand).  quals
+ * flags: OR_ONE_STRAND, OR_FAST (every other read base, per strand),
+ * OR_EXCL_ADJ (top2 never a neighbour of top1).  quals
  * (may be NULL): Phred+33 qualities laid out as the reads, scored with the
  * position-specific pairs of qual_scores at scale qscale. */
 int oracle_scan(const char* genome, uint64_t G, uint32_t F, const char* reads,
@@ -308,7 +315,8 @@ int oracle_scan(const char* genome, uint64_t G, uint32_t F, const char* reads,
   if (!jobs || !th) { free(g); free(jobs); free(th); return OR_ENOMEM; }
   for (int t = 0; t < nthreads; t++) {
     scan_job J = {g, G, F, NF, reads, offsets, n, M, X, (flags & OR_ONE_STRAND) != 0,
-                  (flags & OR_FAST) ? 2u : 1u, quals, qscale, t, nthreads, out, all_v, OR_OK};
+                  (flags & OR_FAST) ? 2u : 1u, quals, qscale, (flags & OR_EXCL_ADJ) != 0,
+                  t, nthreads, out, all_v, OR_OK};
     jobs[t] = J;
     pthread_create(&th[t], NULL, scan_worker, &jobs[t]);
   }
