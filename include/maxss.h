@@ -54,6 +54,15 @@ typedef enum {
                              * first phase scores read positions 0, 2, 4, ... of
                              * each strand only, each against the genome base
                              * at the same distance from the window start      */
+#define MAXSS_EXCLUDE_ADJACENT 8u /* the second-best fragment is never a neighbour
+                             * (frag[0] - 1 or frag[0] + 1) of the best one: a
+                             * read that crosses a junction also scores in the
+                             * neighbouring fragment, at the same locus, and
+                             * would otherwise lower its own mapping quality
+                             * (the ratio test of the first phase).  Reads whose
+                             * second is a neighbour are scanned a second time
+                             * with the three fragments left out.  Not with the
+                             * learned proposal.                              */
 
 /* Scoring and fragmenting parameters, fixed when the genome is indexed.
  *   match        M, score of two equal bases (not N); 1..127.
@@ -63,7 +72,8 @@ typedef enum {
  *                "Byte packing for faster global memory access").
  *   max_read_len longest read any later call may pass; 1..8192 and
  *                max_read_len * match <= 65535 (the scan's 16-bit exact range).
- *   flags        MAXSS_ONE_STRAND, MAXSS_NW_GLOBAL, MAXSS_FAST.
+ *   flags        MAXSS_ONE_STRAND, MAXSS_NW_GLOBAL, MAXSS_FAST,
+ *                MAXSS_EXCLUDE_ADJACENT.
  *   qual_scale   0: plain match / mismatch scores.  > 0: reads carry base
  *                qualities and both phases score with a position-specific
  *                matrix (Methods, paragraph on base qualities and the
@@ -168,7 +178,10 @@ maxss_status maxss_index_info(const maxss_index* index, uint64_t* genome_len,
  * order).  Reads of any lengths may be mixed in one call.
  * out: n records, host or device memory as the reads.  With MAXSS_FAST the
  * windows score every other read base; with qual_scale > 0 they score with the
- * reads' position-specific scores (reads->qual required).
+ * reads' position-specific scores (reads->qual required); with
+ * MAXSS_EXCLUDE_ADJACENT the second fragment is the best one other than
+ * frag[0] - 1, frag[0] and frag[0] + 1 (none, frag[1] = -1, when no other
+ * fragment is left).
  * Errors: EINVAL (NULL pointers, n = 0 is allowed and does nothing, qualities
  * missing on a quality-mode index, a host quality outside '!'..'~'), ETOOLONG
  * (host reads only: a read of length 0 or > max_read_len), ENOMEM, EDEVICE. */
@@ -327,7 +340,8 @@ maxss_status maxss_proposal_scores(const maxss_index* index, maxss_model* model,
  * `margin` is scanned in full instead (fell_back[i] = 1; device, may be
  * NULL).  Records have the layout and tie rules of maxss_scan_reads; they
  * equal the full scan's whenever its top-2 fragments are among the K.
- * Device reads.  Errors: EINVAL (K = 0 or > 4096), ENOMEM, EDEVICE. */
+ * Device reads.  Errors: EINVAL (K = 0 or > 4096, an index with
+ * MAXSS_EXCLUDE_ADJACENT), ENOMEM, EDEVICE. */
 maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxss_model* model,
                                        const maxss_reads* reads, uint32_t K, float margin,
                                        maxss_top2* out, uint8_t* fell_back, void* stream);

@@ -25,6 +25,7 @@ MAXSS_ESTATE = -5
 MAXSS_ONE_STRAND = 1
 MAXSS_NW_GLOBAL = 2
 MAXSS_FAST = 4
+MAXSS_EXCLUDE_ADJACENT = 8
 # scan kernel variants (maxss_scan_kernel_info), by VALU instructions per packed
 # cell pair and step of their inner loop
 MAXSS_KERNEL_STEP_MAX, MAXSS_KERNEL_TWO_STEP, MAXSS_KERNEL_REGISTER_BANK = 0, 1, 2

@@ -314,7 +314,7 @@ extern "C" maxss_status maxss_index_genome(const char* seq, uint64_t len,
   if ((uint64_t)p.max_read_len * (uint64_t)p.match > 65535u)
     return fail(MAXSS_EINVAL, "max_read_len * match = %llu exceeds 65535",
                 (unsigned long long)p.max_read_len * p.match);
-  if (p.flags & ~(MAXSS_ONE_STRAND | MAXSS_NW_GLOBAL | MAXSS_FAST))
+  if (p.flags & ~(MAXSS_ONE_STRAND | MAXSS_NW_GLOBAL | MAXSS_FAST | MAXSS_EXCLUDE_ADJACENT))
     return fail(MAXSS_EINVAL, "unknown flags 0x%x", p.flags);
   if (p.qual_scale > 0) {
     // every position score must fit the scan's int8 score pool, and a whole

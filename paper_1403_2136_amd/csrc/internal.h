@@ -123,6 +123,11 @@ struct ScanWork {
   uint32_t* ctr = nullptr;     // [1]
   int4* partial = nullptr;     // [partial_cap]
   uint64_t partial_cap = 0;    // entries (read x fragment chunk)
+  // MAXSS_EXCLUDE_ADJACENT only: the second pass's fragment left out, read
+  // lengths (0 = not scanned again) and records, per read
+  int32_t* excl = nullptr;     // [cap]
+  uint32_t* lens2 = nullptr;   // [cap]
+  maxss_top2* again = nullptr; // [cap]
 };
 
 // Entries the partial buffer needs for n reads (built-in or forced tiles).

@@ -102,6 +102,7 @@ struct ScanArgs {
   uint32_t step;        // 1, or 2 for the fast scan (every other read base)
   const uint16_t* qsc;  // quality mode: [n][mp_max] (match | mismatch << 8) per position
   uint32_t cq;          // LDS words of position-score pairs per read strand
+  const int32_t* excl;  // NULL, or per read a fragment e: e-1, e, e+1 never enter its top-2
 };
 
 template <int NP>
@@ -754,6 +755,9 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
     // candidate mode: one read per tile, fragments from its sorted list
     const int32_t* clist =
         a.cand ? a.cand + (uint64_t)__builtin_amdgcn_readfirstlane(my_read) * a.K : nullptr;
+    // exclusion pass: this lane's read keeps fragments f with f + 1 - e > 2
+    // (unsigned), i.e. every f but e - 1, e and e + 1
+    const uint32_t ex = (a.excl && lane < rcount) ? (uint32_t)a.excl[my_read] : 0x80000000u;
     // the tile's read codes, both strands, into LDS (N-padded to cw words)
     __syncthreads();
     for (uint32_t idx = lane; idx < rcount * 2 * a.cw; idx += 64) {
@@ -857,7 +861,7 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
       }
       // fragments arrive in increasing id order: strict '>' keeps the
       // smallest id among equal values
-      if (lane < rcount && fv >= 0) {
+      if (lane < rcount && fv >= 0 && f + 1u - ex > 2u) {
         if (fv > t1s) {
           t2s = t1s; t2f = t1f; t1s = fv; t1f = (int)f;
         } else if (fv > t2s) {
@@ -992,6 +996,35 @@ __global__ void merge_kernel(const int4* __restrict__ partial, uint32_t nchunks,
   r.offset[0] = r.offset[1] = -1;
   r.strand[0] = r.strand[1] = -1;
   out[i] = r;
+}
+
+// Reads whose second fragment is a neighbour of the best one are scanned
+// again with the best and its two neighbours left out (lens2 = their length,
+// excl = the best fragment); every other read is skipped (lens2 = 0).
+__global__ void excl_select_kernel(const maxss_top2* __restrict__ top,
+                                   const uint32_t* __restrict__ lens, uint32_t n,
+                                   uint32_t* __restrict__ lens2, int32_t* __restrict__ excl) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int f1 = top[i].frag[0], f2 = top[i].frag[1];
+  const bool again = lens[i] > 0 && f1 >= 0 && f2 >= 0 && (f2 == f1 - 1 || f2 == f1 + 1);
+  lens2[i] = again ? lens[i] : 0u;
+  excl[i] = f1;
+}
+
+// The second fragment of a re-scanned read becomes the best fragment of its
+// exclusion pass (none when every fragment was left out).
+__global__ void excl_combine_kernel(const maxss_top2* __restrict__ again,
+                                    const uint32_t* __restrict__ lens2, uint32_t n,
+                                    maxss_top2* __restrict__ top) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || lens2[i] == 0) return;
+  const maxss_top2 b = again[i];
+  const bool has = b.frag[0] >= 0;
+  top[i].frag[1] = has ? b.frag[0] : -1;
+  top[i].score[1] = has ? b.score[0] : -1;
+  top[i].offset[1] = has ? b.offset[0] : -1;
+  top[i].strand[1] = has ? b.strand[0] : (int8_t)-1;
 }
 
 // Exact re-scan of one winning fragment of one read (int32, one offset per
@@ -1251,6 +1284,13 @@ maxss_status alloc_scan_work(const Index* ix, uint32_t n, uint64_t partial_cap, 
         (s = check_hip(hipMallocAsync((void**)&w->partial, sizeof(int4) * partial_cap, st),
                        "alloc partial")))
       return s;
+    if ((ix->p.flags & MAXSS_EXCLUDE_ADJACENT) &&
+        ((s = check_hip(hipMallocAsync((void**)&w->excl, sizeof(int32_t) * n, st), "alloc excl")) ||
+         (s = check_hip(hipMallocAsync((void**)&w->lens2, sizeof(uint32_t) * n, st),
+                        "alloc lens2")) ||
+         (s = check_hip(hipMallocAsync((void**)&w->again, sizeof(maxss_top2) * n, st),
+                        "alloc again"))))
+      return s;
     return MAXSS_OK;
   }
   w->er.mstride = read_stride(ix);
@@ -1269,11 +1309,16 @@ maxss_status alloc_scan_work(const Index* ix, uint32_t n, uint64_t partial_cap, 
       (s = check_hip(hipMalloc((void**)&w->er.qsc, sizeof(uint16_t) * ((uint64_t)n * w->er.mstride + 64)),
                      "alloc position scores")))
     return s;
+  if ((ix->p.flags & MAXSS_EXCLUDE_ADJACENT) &&
+      ((s = check_hip(hipMalloc((void**)&w->excl, sizeof(int32_t) * n), "alloc excl")) ||
+       (s = check_hip(hipMalloc((void**)&w->lens2, sizeof(uint32_t) * n), "alloc lens2")) ||
+       (s = check_hip(hipMalloc((void**)&w->again, sizeof(maxss_top2) * n), "alloc again"))))
+    return s;
   return MAXSS_OK;
 }
 
 void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st) {
-  void* ps[] = {w->order, w->hist, w->ctr, w->partial};
+  void* ps[] = {w->order, w->hist, w->ctr, w->partial, w->excl, w->lens2, w->again};
   for (void* p : ps) {
     if (!p) continue;
     if (stream_ordered) (void)hipFreeAsync(p, st);
@@ -1290,6 +1335,9 @@ void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st) {
   }
   w->order = w->hist = w->ctr = nullptr;
   w->partial = nullptr;
+  w->excl = nullptr;
+  w->lens2 = nullptr;
+  w->again = nullptr;
 }
 
 // Sort (by `lens`), scan, merge and re-scan for n encoded reads.  Reads with
@@ -1299,7 +1347,7 @@ void release_scan_work(ScanWork* w, bool stream_ordered, hipStream_t st) {
 static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uint32_t* lens,
                               uint32_t n, maxss_top2* dout, const ScanWork& w,
                               const TileOverride* force, const int32_t* cand, uint32_t K,
-                              uint32_t Kc, hipStream_t st) {
+                              uint32_t Kc, hipStream_t st, const int32_t* excl = nullptr) {
   maxss_status s;
   const uint32_t nstrands = (ix->p.flags & MAXSS_ONE_STRAND) ? 1u : 2u;
   const uint32_t mstride = er.mstride;
@@ -1349,6 +1397,7 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   a.step = scan_step(ix);
   a.qsc = t.qs ? er.qsc : nullptr;
   a.cq = t.cq;
+  a.excl = excl;
   if (t.qs && !er.qsc) return fail(MAXSS_ESTATE, "quality mode without position scores");
   s = launch_scan(t, a, st);
   if (s) return s;
@@ -1389,6 +1438,23 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   return check_hip(hipGetLastError(), "rescan_kernel");
 }
 
+// MAXSS_EXCLUDE_ADJACENT: after the full scan, the reads whose second
+// fragment neighbours the best are scanned again with the best fragment and
+// its neighbours left out, and that pass's best becomes their second.
+static maxss_status exclusion_pass(const Index* ix, const EncodedReads& er, const uint32_t* lens,
+                                   uint32_t n, maxss_top2* dout, const ScanWork& w,
+                                   const TileOverride* force, hipStream_t st) {
+  if (!(ix->p.flags & MAXSS_EXCLUDE_ADJACENT)) return MAXSS_OK;
+  if (!w.excl || !w.lens2 || !w.again)
+    return fail(MAXSS_ESTATE, "scan scratch lacks the exclusion buffers");
+  maxss_status s;
+  excl_select_kernel<<<(n + 255) / 256, 256, 0, st>>>(dout, lens, n, w.lens2, w.excl);
+  if ((s = check_hip(hipGetLastError(), "excl_select_kernel"))) return s;
+  if ((s = scan_core(ix, er, w.lens2, n, w.again, w, force, nullptr, 0, 0, st, w.excl))) return s;
+  excl_combine_kernel<<<(n + 255) / 256, 256, 0, st>>>(w.again, w.lens2, n, dout);
+  return check_hip(hipGetLastError(), "excl_combine_kernel");
+}
+
 maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* dout,
                            const ScanWork& w, const TileOverride* force, hipStream_t st) {
   const uint32_t n = r.n;
@@ -1397,13 +1463,16 @@ maxss_status scan_pipeline(const Index* ix, const DeviceReads& r, maxss_top2* do
     return fail(MAXSS_ESTATE, "quality-mode scan of reads without qualities");
   maxss_status s;
   if ((s = encode_reads_into(ix, r, st, w.er))) return s;
-  return scan_core(ix, w.er, w.er.lens, n, dout, w, force, nullptr, 0, 0, st);
+  if ((s = scan_core(ix, w.er, w.er.lens, n, dout, w, force, nullptr, 0, 0, st))) return s;
+  return exclusion_pass(ix, w.er, w.er.lens, n, dout, w, force, st);
 }
 
 maxss_status scan_pipeline_lens(const Index* ix, const EncodedReads& er, const uint32_t* lens,
                                 uint32_t n, maxss_top2* dout, const ScanWork& w, hipStream_t st) {
   if (n == 0) return MAXSS_OK;
-  return scan_core(ix, er, lens, n, dout, w, nullptr, nullptr, 0, 0, st);
+  maxss_status s;
+  if ((s = scan_core(ix, er, lens, n, dout, w, nullptr, nullptr, 0, 0, st))) return s;
+  return exclusion_pass(ix, er, lens, n, dout, w, nullptr, st);
 }
 
 maxss_status candidate_scan(const Index* ix, const EncodedReads& er, const uint32_t* lens,

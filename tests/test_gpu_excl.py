@@ -1,0 +1,129 @@
+"""MAXSS_EXCLUDE_ADJACENT on the GPU: the second-best fragment skips the best
+fragment's neighbours.  Records bit-exact against the oracle's EXCL_ADJ
+scan for the planted closed-form case, random reads with indels over every
+scan kernel (per-step, two-step and register-bank tiles), the fast and
+quality modes, one strand, host and device reads and the plan with its
+graph; the proposal path refuses such an index."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_1403_2136_amd as mx
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("frag", "score", "offset", "strand")
+EX = mx.MAXSS_EXCLUDE_ADJACENT
+
+
+def assert_same(got, ref, what=""):
+    for f in FIELDS:
+        bad = np.nonzero((got[f] != ref[f]).any(axis=1))[0]
+        assert bad.size == 0, "%s: %s differs for %d reads, first %d: gpu %s oracle %s" % (
+            what, f, bad.size, bad[0], got[bad[0]], ref[bad[0]])
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _case(seed, G=40_000, n=90, lens=(40, 90, 150, 250)):
+    g = gen.uniform_genome(G, seed)
+    s = g.seq.copy()
+    s[25_000:26_000] = s[5_000:6_000]                # an exact repeat
+    g = gen.Genome(s, "ex")
+    r = gen.sample_reads(g, n, seed + 1, list(lens), 0.0, 0.3, indel_max=2)
+    return g, r
+
+
+def test_planted_case():
+    rng = np.random.default_rng(5)
+    read = bytes(rng.choice(list(b"ACGT"), 40).astype(np.uint8))
+    g = bytearray(b"N" * (16 * 64))
+    g[5 * 64 + 10:5 * 64 + 50] = read
+    g[6 * 64 + 16:6 * 64 + 46] = read[:30]
+    g[10 * 64 + 10:10 * 64 + 30] = read[:20]
+    off = np.array([0, 40], np.uint64)
+    ix = mx.Index(bytes(g), 64, 40, flags=EX)
+    got = ix.scan(read, off)
+    ix.close()
+    assert list(got[0]["frag"]) == [5, 10] and list(got[0]["score"]) == [40, 20]
+    assert_same(got, oracle.scan(bytes(g), 64, read, off, flags=oracle.EXCL_ADJ), "planted")
+
+
+@pytest.mark.parametrize("F,np_", [(512, 0), (2048, 0), (2048, 8), (4096, 32), (48, 0)])
+def test_random_reads_every_kernel(F, np_):
+    g, r = _case(71 + F % 97)
+    ref = oracle.scan(g.seq, F, r.seq, r.offsets, flags=oracle.EXCL_ADJ, nthreads=8)
+    plain = oracle.scan(g.seq, F, r.seq, r.offsets, nthreads=8)
+    ix = mx.Index(g.seq, F, 250, flags=EX)
+    if np_:
+        ix.set_tiles(np_, 0, 0)
+    got = ix.scan(r.seq, r.offsets)
+    ix.close()
+    assert_same(got, ref, "F=%d NP=%d" % (F, np_))
+    changed = (ref["frag"][:, 1] != plain["frag"][:, 1]).sum()
+    assert changed > 0, "no read had an adjacent second fragment"
+
+
+@pytest.mark.parametrize("flags,oflags", [
+    (mx.MAXSS_FAST, oracle.FAST),
+    (mx.MAXSS_ONE_STRAND, oracle.ONE_STRAND),
+])
+def test_with_fast_and_one_strand(flags, oflags):
+    g, r = _case(83)
+    ref = oracle.scan(g.seq, 2048, r.seq, r.offsets, flags=oflags | oracle.EXCL_ADJ, nthreads=8)
+    ix = mx.Index(g.seq, 2048, 250, flags=flags | EX)
+    assert_same(ix.scan(r.seq, r.offsets), ref, "flags %d" % flags)
+    ix.close()
+
+
+def test_with_qualities():
+    g, r = _case(89)
+    q = gen.sample_qualities(r, 90)
+    ref = oracle.scan(g.seq, 2048, r.seq, r.offsets, 5, -4, flags=oracle.EXCL_ADJ, nthreads=8,
+                      quals=q, qscale=10)
+    ix = mx.Index(g.seq, 2048, 250, 5, -4, -26, flags=EX, qual_scale=10)
+    assert_same(ix.scan(r.seq, r.offsets, qual=q), ref, "qualities")
+    ix.close()
+
+
+def test_plan_graph_and_device_reads():
+    torch = _torch()
+    g, r = _case(97, n=120)
+    ref = oracle.scan(g.seq, 2048, r.seq, r.offsets, flags=oracle.EXCL_ADJ, nthreads=8)
+    ix = mx.Index(g.seq, 2048, 250, flags=EX)
+    s = torch.from_numpy(np.array(r.seq)).cuda()
+    o = torch.from_numpy(r.offsets.astype(np.int64)).cuda()
+    out = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(s, o, out, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert_same(out.cpu().numpy().view(mx.TOP2_DTYPE), ref, "device reads")
+    plan = mx.Plan(ix, capacity=r.n, pad=50, cigar_stride=512)
+    top = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        top.fill_(0xAB)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.run(s, o, top, stream=stream, graph=True)
+        stream.synchronize()
+        assert_same(top.cpu().numpy().view(mx.TOP2_DTYPE), ref, "graph replay %d" % rep)
+    plan.close()
+    ix.close()
+
+
+def test_proposal_refuses_the_flag():
+    torch = _torch()
+    g, r = _case(101, n=8)
+    ix = mx.Index(g.seq, 2048, 250, flags=EX)
+    m = mx.Model(gen.mlp_init(3))
+    s = torch.from_numpy(np.array(r.seq)).cuda()
+    o = torch.from_numpy(r.offsets.astype(np.int64)).cuda()
+    out = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mx.MaxssError):
+        m.scan(ix, s, o, 16, 0.0, out)
+    m.close()
+    ix.close()
