@@ -233,6 +233,39 @@ def qual_leg(w, seq, off, full_scan_ms, stream, scale: int = 10):
     return res
 
 
+def excl_leg(w, seq, off, top_full, full_scan_ms, stream):
+    """Second-best fragment with the best one's neighbours left out: the
+    reads whose plain second is a neighbour are scanned again.  Reports the
+    scan kernel time of both passes against the plain scan and how many
+    reads took the second pass."""
+    import numpy as np
+    import torch
+
+    import paper_1403_2136_amd as mx
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap,
+                  flags=mx.MAXSS_EXCLUDE_ADJACENT)
+    n = w.reads.n
+    out = torch.empty(n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(seq, off, out, stream=stream)
+    torch.cuda.synchronize()
+    mx.maxss_profile_enable(True)
+    ix.scan(seq, off, out, stream=stream)
+    torch.cuda.synchronize()
+    ms, k = mx.maxss_profile_read("scan")
+    mx.maxss_profile_enable(False)
+    ix.close()
+    ref = top_full.cpu().numpy().view(mx.TOP2_DTYPE)
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    f1, f2 = ref["frag"][:, 0].astype(np.int64), ref["frag"][:, 1].astype(np.int64)
+    again = int(((f1 >= 0) & (f2 >= 0) & (np.abs(f2 - f1) == 1)).sum())
+    res = {"scan_ms_both_passes": round(ms, 3), "scan_launches": k,
+           "plain_scan_ms_per_launch": round(full_scan_ms, 3),
+           "overhead": round(ms / full_scan_ms, 4), "reads_scanned_again": again,
+           "reads": n, "second_changed": int((got["frag"][:, 1] != ref["frag"][:, 1]).sum())}
+    log("exclude adjacent: %s" % res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +282,9 @@ def main():
                     help="skip the base-quality scoring leg")
     ap.add_argument("--no-fast", action="store_true",
                     help="skip the MaxSSmap_fast leg (every other read base scored)")
+    ap.add_argument("--no-excl", action="store_true",
+                    help="skip the leg that leaves the best fragment's neighbours out of the "
+                         "second-best")
     ap.add_argument("--train-reads", type=int, default=200_000)
     ap.add_argument("--damaged-train-reads", type=int, default=22_000,
                     help="training + validation reads of the damaged workload's proposal leg "
@@ -411,6 +447,8 @@ def main():
         res["fast"] = fast_leg(w, seq, off, top, scan_s * 1e3, stream)
     if not args.no_qual and not batched:
         res["qual"] = qual_leg(w, seq, off, scan_s * 1e3, stream)
+    if not args.no_excl and not batched:
+        res["exclude_adjacent"] = excl_leg(w, seq, off, top, scan_s * 1e3, stream)
     if not args.no_proposal and w.name in ("bacterial", "damaged"):
         res["proposal"] = proposal_leg(ix, w, seq, off, top, stream, args)
     if not args.no_cpu_baseline:

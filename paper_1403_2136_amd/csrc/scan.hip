@@ -1450,7 +1450,12 @@ static maxss_status exclusion_pass(const Index* ix, const EncodedReads& er, cons
   maxss_status s;
   excl_select_kernel<<<(n + 255) / 256, 256, 0, st>>>(dout, lens, n, w.lens2, w.excl);
   if ((s = check_hip(hipGetLastError(), "excl_select_kernel"))) return s;
-  if ((s = scan_core(ix, er, w.lens2, n, w.again, w, force, nullptr, 0, 0, st, w.excl))) return s;
+  // Few reads take this pass (their count stays on the device), so tiles of
+  // one read and as many fragment chunks as the partial buffer holds spread
+  // them over the resident waves; the offset pairs per lane stay as set.
+  const TileOverride* base = force ? force : &ix->tune;
+  const TileOverride one{base->NP, 1u, 1024u};
+  if ((s = scan_core(ix, er, w.lens2, n, w.again, w, &one, nullptr, 0, 0, st, w.excl))) return s;
   excl_combine_kernel<<<(n + 255) / 256, 256, 0, st>>>(w.again, w.lens2, n, dout);
   return check_hip(hipGetLastError(), "excl_combine_kernel");
 }
