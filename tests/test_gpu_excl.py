@@ -127,3 +127,33 @@ def test_proposal_refuses_the_flag():
         m.scan(ix, s, o, 16, 0.0, out)
     m.close()
     ix.close()
+
+
+def test_mapping_quality_of_a_junction_read():
+    # best 40 in fragment 5, 38 in its neighbour 6, 20 in fragment 10: the
+    # plain ratio 38/40 fails the 0.9 test; without the neighbour the ratio
+    # is 20/40 and MAPQ is 100
+    torch = _torch()
+    from oracle import sam
+    rng = np.random.default_rng(7)
+    read = bytes(rng.choice(list(b"ACGT"), 40).astype(np.uint8))
+    g = bytearray(b"N" * (16 * 64))
+    g[5 * 64 + 10:5 * 64 + 50] = read
+    g[6 * 64 + 16:6 * 64 + 54] = read[:38]
+    g[10 * 64 + 10:10 * 64 + 30] = read[:20]
+    off = np.array([0, 40], np.uint64)
+    res = {}
+    for flags in (0, EX):
+        ix = mx.Index(bytes(g), 64, 40, flags=flags)
+        top = ix.scan(read, off)
+        ix.close()
+        d = torch.from_numpy(top.view(np.uint8).copy()).cuda()
+        q = torch.zeros(1, dtype=torch.uint8, device="cuda")
+        m = torch.zeros(1, dtype=torch.uint8, device="cuda")
+        mx.maxss_mapq(d, 1, q, m)
+        torch.cuda.synchronize()
+        s1, s2 = int(top[0]["score"][0]), int(top[0]["score"][1])
+        assert int(q.item()) == sam.mapq(s1, s2) and bool(m.item()) == sam.is_mapped(s1, s2)
+        res[flags] = (s2, int(q.item()), int(m.item()))
+    assert res[0] == (38, 7, 0)
+    assert res[EX] == (20, 100, 1)
