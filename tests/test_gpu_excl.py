@@ -157,3 +157,13 @@ def test_mapping_quality_of_a_junction_read():
         res[flags] = (s2, int(q.item()), int(m.item()))
     assert res[0] == (38, 7, 0)
     assert res[EX] == (20, 100, 1)
+
+
+def test_autotuner_keeps_the_records():
+    g, r = _case(113, n=128)
+    ref = oracle.scan(g.seq, 2048, r.seq, r.offsets, flags=oracle.EXCL_ADJ, nthreads=8)
+    ix = mx.Index(g.seq, 2048, 250, flags=EX)
+    res = ix.autotune(r.seq, r.offsets)
+    assert res["tried"] > 0 and res["rejected"] == 0
+    assert_same(ix.scan(r.seq, r.offsets), ref, "after autotune")
+    ix.close()
