@@ -92,3 +92,16 @@ def test_host_offsets_checked_against_buffer(L):
         mx._host_csr(b"ACGT", [0, 3, 2])
     s, off = mx._host_csr(b"ACGT", [0, 2, 4])
     assert s.size == 4 and off.tolist() == [0, 2, 4]
+
+
+def test_header_constants_match_the_binding():
+    txt = open(os.path.join(ROOT, "include", "maxss.h")).read()
+    defs = dict(re.findall(r"#define\s+(MAXSS_[A-Z0-9_]+)\s+(-?\d+)u?\b", txt))
+    assert {"MAXSS_ONE_STRAND", "MAXSS_NW_GLOBAL", "MAXSS_FAST", "MAXSS_EXCLUDE_ADJACENT",
+            "MAXSS_KERNEL_REGISTER_BANK"} <= set(defs)
+    for name, value in defs.items():
+        if hasattr(mx, name):
+            assert getattr(mx, name) == int(value), name
+    flags = [int(defs[k]) for k in ("MAXSS_ONE_STRAND", "MAXSS_NW_GLOBAL", "MAXSS_FAST",
+                                    "MAXSS_EXCLUDE_ADJACENT")]
+    assert len(set(flags)) == 4 and all(f & (f - 1) == 0 for f in flags)  # distinct bits
