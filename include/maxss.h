@@ -61,8 +61,8 @@ typedef enum {
                              * would otherwise lower its own mapping quality
                              * (the ratio test of the first phase).  Reads whose
                              * second is a neighbour are scanned a second time
-                             * with the three fragments left out.  Not with the
-                             * learned proposal.                              */
+                             * with the three fragments left out (through the
+                             * learned proposal: among the same candidates). */
 
 /* Scoring and fragmenting parameters, fixed when the genome is indexed.
  *   match        M, score of two equal bases (not N); 1..127.
@@ -340,8 +340,9 @@ maxss_status maxss_proposal_scores(const maxss_index* index, maxss_model* model,
  * `margin` is scanned in full instead (fell_back[i] = 1; device, may be
  * NULL).  Records have the layout and tie rules of maxss_scan_reads; they
  * equal the full scan's whenever its top-2 fragments are among the K.
- * Device reads.  Errors: EINVAL (K = 0 or > 4096, an index with
- * MAXSS_EXCLUDE_ADJACENT), ENOMEM, EDEVICE. */
+ * With MAXSS_EXCLUDE_ADJACENT the second is the best candidate other than
+ * the best one's neighbours.  Device reads.  Errors: EINVAL (K = 0 or >
+ * 4096), ENOMEM, EDEVICE. */
 maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxss_model* model,
                                        const maxss_reads* reads, uint32_t K, float margin,
                                        maxss_top2* out, uint8_t* fell_back, void* stream);

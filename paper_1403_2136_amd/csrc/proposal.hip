@@ -956,9 +956,6 @@ extern "C" maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxs
   if (!ix || !m || !reads || !out) return fail(MAXSS_EINVAL, "NULL argument");
   if (!reads->on_device) return fail(MAXSS_EINVAL, "the proposal path takes device reads");
   if (K == 0 || K > 4096) return fail(MAXSS_EINVAL, "K must be in 1..4096");
-  if (ix->p.flags & MAXSS_EXCLUDE_ADJACENT)
-    return fail(MAXSS_EINVAL, "the proposal path keeps the plain top-2 (index has "
-                              "MAXSS_EXCLUDE_ADJACENT)");
   if (maxss_status q = require_quals(ix, reads)) return q;
   const uint32_t n = reads->n;
   if (n == 0) return MAXSS_OK;

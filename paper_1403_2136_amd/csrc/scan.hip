@@ -1438,12 +1438,15 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   return check_hip(hipGetLastError(), "rescan_kernel");
 }
 
-// MAXSS_EXCLUDE_ADJACENT: after the full scan, the reads whose second
-// fragment neighbours the best are scanned again with the best fragment and
-// its neighbours left out, and that pass's best becomes their second.
+// MAXSS_EXCLUDE_ADJACENT: after the full scan (or the candidate scan, cand
+// != NULL), the reads whose second fragment neighbours the best are scanned
+// again (over the same fragments) with the best fragment and its neighbours
+// left out, and that pass's best becomes their second.
 static maxss_status exclusion_pass(const Index* ix, const EncodedReads& er, const uint32_t* lens,
                                    uint32_t n, maxss_top2* dout, const ScanWork& w,
-                                   const TileOverride* force, hipStream_t st) {
+                                   const TileOverride* force, hipStream_t st,
+                                   const int32_t* cand = nullptr, uint32_t K = 0,
+                                   uint32_t Kc = 0) {
   if (!(ix->p.flags & MAXSS_EXCLUDE_ADJACENT)) return MAXSS_OK;
   if (!w.excl || !w.lens2 || !w.again)
     return fail(MAXSS_ESTATE, "scan scratch lacks the exclusion buffers");
@@ -1455,7 +1458,9 @@ static maxss_status exclusion_pass(const Index* ix, const EncodedReads& er, cons
   // them over the resident waves; the offset pairs per lane stay as set.
   const TileOverride* base = force ? force : &ix->tune;
   const TileOverride one{base->NP, 1u, 1024u};
-  if ((s = scan_core(ix, er, w.lens2, n, w.again, w, &one, nullptr, 0, 0, st, w.excl))) return s;
+  if ((s = scan_core(ix, er, w.lens2, n, w.again, w, cand ? nullptr : &one, cand, K, Kc, st,
+                     w.excl)))
+    return s;
   excl_combine_kernel<<<(n + 255) / 256, 256, 0, st>>>(w.again, w.lens2, n, dout);
   return check_hip(hipGetLastError(), "excl_combine_kernel");
 }
@@ -1484,7 +1489,9 @@ maxss_status candidate_scan(const Index* ix, const EncodedReads& er, const uint3
                             uint32_t n, const int32_t* cand, uint32_t K, uint32_t Kc,
                             maxss_top2* dout, const ScanWork& w, hipStream_t st) {
   if (n == 0) return MAXSS_OK;
-  return scan_core(ix, er, lens, n, dout, w, nullptr, cand, K, Kc, st);
+  maxss_status s;
+  if ((s = scan_core(ix, er, lens, n, dout, w, nullptr, cand, K, Kc, st))) return s;
+  return exclusion_pass(ix, er, lens, n, dout, w, nullptr, st, cand, K, Kc);
 }
 
 }  // namespace maxss

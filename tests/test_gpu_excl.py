@@ -2,8 +2,8 @@
 fragment's neighbours.  Records bit-exact against the oracle's EXCL_ADJ
 scan for the planted closed-form case, random reads with indels over every
 scan kernel (per-step, two-step and register-bank tiles), the fast and
-quality modes, one strand, host and device reads and the plan with its
-graph; the proposal path refuses such an index."""
+quality modes, one strand, host and device reads, the plan with its graph,
+the autotuner and the learned proposal's candidate scan."""
 import numpy as np
 import pytest
 
@@ -115,16 +115,59 @@ def test_plan_graph_and_device_reads():
     ix.close()
 
 
-def test_proposal_refuses_the_flag():
+def _best(vals, fr):
+    """(fragment, value) of the highest value among fr, smallest id on ties;
+    (-1, -1) when fr is empty."""
+    fr = sorted(int(f) for f in fr)
+    if not fr:
+        return -1, -1
+    f = max(fr, key=lambda x: (int(vals[x]), -x))
+    return f, int(vals[f])
+
+
+def test_proposal_with_the_flag():
+    """Through the learned proposal: a read that keeps its candidates gets
+    the best candidate and the best candidate other than that one's
+    neighbours; a read that falls back gets the full scan's record."""
     torch = _torch()
-    g, r = _case(101, n=8)
+    g, r = _case(101, G=120_000, n=96)
     ix = mx.Index(g.seq, 2048, 250, flags=EX)
     m = mx.Model(gen.mlp_init(3))
     s = torch.from_numpy(np.array(r.seq)).cuda()
     o = torch.from_numpy(r.offsets.astype(np.int64)).cuda()
-    out = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
-    with pytest.raises(mx.MaxssError):
-        m.scan(ix, s, o, 16, 0.0, out)
+    K = 8
+    full_ex = oracle.scan(g.seq, 2048, r.seq, r.offsets, flags=oracle.EXCL_ADJ, nthreads=8)
+    _, vals = oracle.scan(g.seq, 2048, r.seq, r.offsets, nthreads=8, want_values=True)
+    for tau, all_fall in ((-1.0, False), (float("inf"), True)):
+        out = torch.zeros(r.n * 32, dtype=torch.uint8, device="cuda")
+        fb = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+        cand = torch.zeros(r.n * K, dtype=torch.int32, device="cuda")
+        mg = torch.zeros(r.n, dtype=torch.float32, device="cuda")
+        fb2 = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+        m.scan(ix, s, o, K, tau, out, fb)
+        m.candidates(ix, s, o, K, tau, cand, mg, fb2)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+        fb = fb.cpu().numpy()
+        cand = cand.cpu().numpy().reshape(r.n, K)
+        assert (fb == 1).all() if all_fall else (fb == 0).all()
+        if all_fall:
+            assert_same(got, full_ex, "all reads fall back")
+            continue
+        seen = 0
+        for i in range(r.n):
+            c = [f for f in cand[i] if f >= 0]
+            f1, s1 = _best(vals[i], c)
+            f2, s2 = _best(vals[i], [f for f in c if abs(f - f1) > 1])
+            assert got["frag"][i].tolist() == [f1, f2], i
+            assert got["score"][i].tolist() == [s1, s2], i
+            seen += any(abs(f - f1) == 1 for f in c)
+            for e in (0, 1):
+                for k in (0, 1):
+                    if got["frag"][i][e] == full_ex["frag"][i][k] and got["frag"][i][e] >= 0:
+                        assert got["offset"][i][e] == full_ex["offset"][i][k], (i, e, k)
+                        assert got["strand"][i][e] == full_ex["strand"][i][k], (i, e, k)
+        assert seen > 0
     m.close()
     ix.close()
 
