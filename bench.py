@@ -7,6 +7,11 @@ of the two winners) followed by maxss_align_top (NW of every read on its best
 fragment).  The metric is MaxSS GCUPS = (sum over reads of 2 * G * m) / step
 time / 1e9 (both strands, every genome start position).
 
+Beside the step, on the same reads: the scan of host buffers (PCIe
+included), MaxSSmap_fast, base-quality scoring, the neighbour exclusion of
+the second-best fragment, the learned proposal against the full scan, and
+the CPU oracle on a sample (each leg can be switched off).
+
 Prints one JSON line.  `--gpus N` with N > 1 is refused: the benchmark
 measures one GPU (the scan shards by reads across GPUs with no collective).
 """
