@@ -210,3 +210,41 @@ def test_autotuner_keeps_the_records():
     assert res["tried"] > 0 and res["rejected"] == 0
     assert_same(ix.scan(r.seq, r.offsets), ref, "after autotune")
     ix.close()
+
+
+@pytest.mark.slow
+def test_bacterial_full_size_sampled():
+    """The full 100,000-read bacterial workload with and without the flag in
+    the bench's launch configuration: every read's second is no neighbour of
+    its best, reads with a plain second elsewhere keep their records, and 24
+    re-scanned reads plus 8 others are checked against the oracle."""
+    torch = _torch()
+
+    def scan_device(ix, seq, offsets):
+        s = torch.from_numpy(np.ascontiguousarray(seq, dtype=np.uint8)).cuda()
+        o = torch.from_numpy(np.ascontiguousarray(offsets).astype(np.int64)).cuda()
+        out = torch.empty((len(offsets) - 1) * 32, dtype=torch.uint8, device="cuda")
+        ix.scan(s, o, out, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        return out.cpu().numpy().view(mx.TOP2_DTYPE)
+
+    w = gen.workload("bacterial")
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap)
+    plain = scan_device(ix, w.reads.seq, w.reads.offsets)
+    ix.close()
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap, flags=EX)
+    got = scan_device(ix, w.reads.seq, w.reads.offsets)
+    ix.close()
+    f1, f2 = got["frag"][:, 0].astype(np.int64), got["frag"][:, 1].astype(np.int64)
+    assert ((f2 < 0) | (np.abs(f2 - f1) > 1)).all()
+    adj = np.abs(plain["frag"][:, 1].astype(np.int64) - plain["frag"][:, 0]) == 1
+    assert 0 < adj.sum() < w.reads.n
+    assert (got[~adj].tobytes() == plain[~adj].tobytes())
+    assert (got["frag"][:, 0] == plain["frag"][:, 0]).all()
+    ia, io = np.nonzero(adj)[0], np.nonzero(~adj)[0]
+    idx = np.sort(np.concatenate([ia[np.linspace(0, ia.size - 1, 24).astype(np.int64)],
+                                  io[np.linspace(0, io.size - 1, 8).astype(np.int64)]]))
+    sub = w.reads.subset(idx)
+    ref = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, flags=oracle.EXCL_ADJ,
+                      nthreads=16)
+    assert_same(got[idx], ref, "bacterial sample")
