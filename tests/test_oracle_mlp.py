@@ -1,6 +1,8 @@
 """Pins of the float64 proposal oracle: brute-force 4-mer counts, library
 bfloat16 rounding, the decomposition identity, finite-difference gradients,
-Adam's closed-form first step and a sort-based top-K."""
+Adam's closed-form first step, its constant-gradient closed form and
+torch.optim.Adam over several steps, a hand-computed forward with both
+biases, a sort-based top-K and top-2 among candidates."""
 import itertools
 
 import numpy as np
@@ -145,3 +147,125 @@ def test_params_layout_size():
     assert p.dtype == np.float32 and p.size == mlp.N_PARAMS
     W1, b1, w2, b2 = mlp.unpack(p)
     assert W1.shape == (256, 512) and b1.shape == (256,) and w2.shape == (256,)
+
+
+# ---- pins of top2_among, Adam past its first step and the forward biases
+
+def test_top2_among_matches_lexsort_on_tie_heavy_rows():
+    """Top-2 among candidates by (value desc, id asc): against a lexsort of
+    the candidate values.  Values in 0..3 make most rows tie at the top, so a
+    reversed id rule or a max that keeps the last tie fails."""
+    r = np.random.default_rng(11)
+    for trial in range(300):
+        NF = int(r.integers(2, 40))
+        vals = r.integers(0, 4, NF)
+        k = int(r.integers(1, NF + 1))
+        cand = np.sort(r.choice(NF, k, replace=False))
+        f1, s1, f2, s2 = mlp.top2_among(vals, cand)
+        order = cand[np.lexsort((cand, -vals[cand]))]
+        assert (f1, s1) == (int(order[0]), int(vals[order[0]]))
+        if k == 1:
+            assert (f2, s2) == (-1, -1)
+        else:
+            assert (f2, s2) == (int(order[1]), int(vals[order[1]]))
+    # a hand-checked row: three fragments tie at 3; ids 4 and 7 are the two smallest
+    assert mlp.top2_among(np.array([0, 2, 1, 0, 3, 2, 0, 3, 3]), [8, 7, 4, 1]) == (4, 3, 7, 3)
+
+
+def test_top2_among_all_fragments_is_the_scan_top2():
+    """Over every fragment, top2_among of the oracle's exact value row gives
+    the scan's own top-2 (fragment and score); over a candidate set holding
+    the scan's two winners it gives the same; over a set without the winner
+    it gives the best remaining fragment of the value row."""
+    import oracle
+    g = gen.bacterial_genome(7, base_len=60_000)
+    r = gen.sample_reads(g, 24, 8, [60], 0.0, 0.2, indel_max=1)
+    F = 512
+    top, vals = oracle.scan(g.seq, F, r.seq, r.offsets, want_values=True)
+    NF = vals.shape[1]
+    rng = np.random.default_rng(12)
+    for i in range(r.n):
+        f1, s1, f2, s2 = mlp.top2_among(vals[i], range(NF))
+        assert (f1, s1, f2, s2) == (top["frag"][i][0], top["score"][i][0],
+                                    top["frag"][i][1], top["score"][i][1])
+        extra = rng.choice(NF, 10, replace=False)
+        cand = np.unique(np.concatenate([extra, top["frag"][i]]))
+        assert mlp.top2_among(vals[i], cand) == (f1, s1, f2, s2)
+        rest = [f for f in range(NF) if f != f1]
+        g1, t1, _, _ = mlp.top2_among(vals[i], rest)
+        assert (g1, t1) == (f2, s2)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient g, both bias-corrected moments equal g and g^2
+    exactly at every step t (the EMA of a constant, divided by 1 - beta^t), so
+    every step moves theta by lr * g / (|g| + eps).  A bias correction with a
+    wrong power of beta (e.g. beta instead of beta^t) fails from step 2 on."""
+    a = mlp.Adam(3)
+    th = np.array([0.25, -1.0, 2.0])
+    g = np.array([0.5, -3.0, 1e-4])
+    lr = 0.01
+    for t in range(1, 6):
+        th_new = a.step(th, g, lr)
+        assert np.allclose(th - th_new, lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0), t
+        th = th_new
+
+
+def test_adam_three_steps_match_torch_adam():
+    """Three steps with changing gradients against torch.optim.Adam (float64,
+    same betas and eps): the bias correction at t = 2 and 3 is pinned to an
+    independent implementation of the same published update."""
+    import torch
+    r = np.random.default_rng(13)
+    th0 = r.normal(size=50)
+    grads = [r.normal(size=50) * s for s in (1.0, -2.5, 0.3)]
+    lr = 3e-3
+    a = mlp.Adam(50)
+    th = th0.copy()
+    p = torch.nn.Parameter(torch.from_numpy(th0.copy()))
+    opt = torch.optim.Adam([p], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    for g in grads:
+        th = a.step(th, g, lr)
+        p.grad = torch.from_numpy(g.copy())
+        opt.step()
+        assert np.allclose(th, p.detach().numpy(), rtol=0, atol=1e-14)
+    # by hand, element 0 of a scalar run g = (1, -2, 0.5), lr 0.1: after step 2
+    # m = -0.11, v = 0.004999, m_hat = -0.11/0.19, v_hat = 0.004999/0.001999
+    s = mlp.Adam(1)
+    x = s.step(np.zeros(1), np.array([1.0]), 0.1)
+    x = s.step(x, np.array([-2.0]), 0.1)
+    step2 = (-0.11 / 0.19) / (np.sqrt(0.004999 / 0.001999) + 1e-8)
+    assert abs(x[0] - (-0.1 / (1 + 1e-8) - 0.1 * step2)) < 1e-14
+
+
+def test_forward_hand_computed_with_biases_and_negative_preactivation():
+    """y = w2 . ReLU(W1 z + b1) + b2 on a hand-sized case: unit 0 is active
+    (pre 1 + 2*0.5 + 0.5 = 2.5), unit 1 is negative (pre -1 + 0.25 = -0.75,
+    contributes 0), unit 2 is active through its bias only (0.125); all other
+    units have zero weights and a zero bias.  y = 2*2.5 + 0 + 4*0.125 - 0.75
+    = 4.75.  Dropping b2 gives 5.5; dropping b1 gives 3.25; no ReLU gives
+    0.95."""
+    W1 = np.zeros((256, 512))
+    b1 = np.zeros(256)
+    w2 = np.zeros(256)
+    W1[0, 3] = 1.0
+    W1[0, 256 + 5] = 2.0
+    b1[0] = 0.5
+    W1[1, 3] = -1.0
+    b1[1] = 0.25
+    w2[1] = 5.0
+    b1[2] = 0.125
+    w2[0], w2[2] = 2.0, 4.0
+    p = mlp.pack(W1, b1, w2, -0.75)
+    vr = np.zeros(256)
+    vr[3] = 1.0
+    vf = np.zeros(256)
+    vf[5] = 0.5
+    y, pre, h = mlp.forward(p, np.concatenate([vr, vf])[None, :])
+    assert y[0] == 4.75
+    assert pre[0, 0] == 2.5 and pre[0, 1] == -0.75 and h[0, 1] == 0.0
+    assert mlp.forward_decomposed(p, vr[None, :], vf[None, :])[0, 0] == 4.75
+    # the training forward keeps b2 in every logit: with a zero fragment
+    # profile unit 0's pre-activation is 1 + 0.5 = 1.5, so y = 3 + 0.5 - 0.75
+    loss, yl, _ = mlp.loss_and_grad(p, vr[None, :], np.stack([vf, np.zeros(256)])[None, :, :])
+    assert yl[0, 0] == 4.75 and yl[0, 1] == 2.75
