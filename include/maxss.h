@@ -188,6 +188,28 @@ maxss_status maxss_index_info(const maxss_index* index, uint64_t* genome_len,
 maxss_status maxss_scan_reads(const maxss_index* index, const maxss_reads* reads,
                               maxss_top2* out, void* stream);
 
+/* maxss_scan_reads without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same records as maxss_scan_reads, written to `out`
+ * (n device records), asynchronously on `stream`; reads->on_device must be 1.
+ * Every scratch buffer of the call (encoded reads, length order and
+ * histogram, work counter, per-chunk partial top-2, and with
+ * MAXSS_EXCLUDE_ADJACENT the second pass's buffers) comes from one 64 MiB
+ * device array that the library holds per device until the process ends.
+ * A call needs, in 256-byte aligned pieces, 4*(n*2*(S/8)+64) + (n*S+64) +
+ * 4*(n+1) [+ 2*(n*S+64) with qual_scale > 0] + 4*n + 4*(max_read_len+1) + 4
+ * [+ 40*n with MAXSS_EXCLUDE_ADJACENT] + at least 16*n bytes, where
+ * S = max_read_len rounded up to 64 (about 27 MB for 100,000 reads with
+ * max_read_len <= 128); what is left becomes partial top-2 space, and fewer
+ * fragment chunks per read are used when it is small (same records).
+ * All calls on one device share the array: calls that overlap on one device
+ * (different streams or host threads) race and must be serialised by the
+ * caller.  Errors: EINVAL (NULL, host reads, qualities missing on a
+ * quality-mode index, a batch needing more than the 64 MiB), ESTATE (index
+ * on another device), EDEVICE. */
+maxss_status maxss_scan_reads_noalloc(const maxss_index* index, const maxss_reads* reads,
+                                      maxss_top2* out, void* stream);
+
 /* Second phase (Methods, "Second phase of MaxSSmap"): for every read,
  * Needleman-Wunsch with a linear gap of the read, in the orientation of
  * top[i].strand[0], against the genome region

@@ -69,6 +69,7 @@ class Reads(ctypes.Structure):
 
 # every function declared in include/maxss.h
 EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_scan_reads",
+           "maxss_scan_reads_noalloc",
            "maxss_align_top", "maxss_plan_create", "maxss_plan_free", "maxss_plan_run",
            "maxss_plan_run_graph", "maxss_autotune", "maxss_index_set_tiles",
            "maxss_scan_kernel_info",
@@ -105,6 +106,9 @@ def lib():
                                        c.POINTER(c.c_uint32)]
         L.maxss_scan_reads.restype = c.c_int
         L.maxss_scan_reads.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p, c.c_void_p]
+        L.maxss_scan_reads_noalloc.restype = c.c_int
+        L.maxss_scan_reads_noalloc.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p,
+                                               c.c_void_p]
         L.maxss_align_top.restype = c.c_int
         L.maxss_align_top.argtypes = [c.c_void_p, c.POINTER(Reads), c.c_void_p, c.c_uint32,
                                       c.c_void_p, c.c_void_p, c.c_uint64, c.c_void_p]
@@ -320,6 +324,16 @@ def maxss_scan_reads(handle: int, seq, offsets, out=None, stream=None, qual=None
     _check(lib().maxss_scan_reads(h_(handle), ctypes.byref(r), _buf(res, 32 * n, "out"),
                                   _stream_handle(stream)))
     return res
+
+
+def maxss_scan_reads_noalloc(handle: int, seq, offsets, out, stream=None, qual=None):
+    """maxss_scan_reads on device reads (torch tensors) with the library's
+    fixed per-device scratch instead of allocations; `out` is a device tensor
+    of n*32 bytes.  Calls that overlap on one device race."""
+    r = _reads_struct(seq, offsets, True, qual)
+    _check(lib().maxss_scan_reads_noalloc(h_(handle), ctypes.byref(r), _buf(out, 32 * r.n, "out"),
+                                          _stream_handle(stream)))
+    return out
 
 
 def maxss_align_top(handle: int, seq, offsets, top, pad: int = 100, cigar_stride: int = 512,

@@ -79,6 +79,7 @@ def test_null_arguments(L):
     p = mx.Params(1, -1, -2, 16, 10, 0)
     assert L.maxss_index_genome(None, 4, ctypes.byref(p), None) == mx.MAXSS_EINVAL
     assert L.maxss_scan_reads(None, None, None, None) == mx.MAXSS_EINVAL
+    assert L.maxss_scan_reads_noalloc(None, None, None, None) == mx.MAXSS_EINVAL
     assert L.maxss_align_top(None, None, None, 100, None, None, 16, None) == mx.MAXSS_EINVAL
     assert L.maxss_index_info(None, None, None, None) == mx.MAXSS_EINVAL
     L.maxss_index_free(None)   # no-op
