@@ -7,10 +7,18 @@ of the two winners) followed by maxss_align_top (NW of every read on its best
 fragment).  The metric is MaxSS GCUPS = (sum over reads of 2 * G * m) / step
 time / 1e9 (both strands, every genome start position).
 
+The roofline object prices the scan kernel at a fixed algorithmic unit, one
+16-bit lane operation per cell (the Kadane step's saturating add), against
+the packed 16-bit VALU peak derived from 256 CUs x 64 lanes x 2.4 GHz x 2;
+beside it are the peak measured on the GPU by maxss_roof_int16 and the
+launched kernel's own instructions per cell.
+
 Beside the step, on the same reads: the scan of host buffers (PCIe
 included), MaxSSmap_fast, base-quality scoring, the neighbour exclusion of
-the second-best fragment, the learned proposal against the full scan, and
-the CPU oracle on a sample (each leg can be switched off).
+the second-best fragment and the learned proposal against the full scan;
+then the batched path on the 248 Mbp chromosome-scale workload (persistent
+scan, captured graph, autotuned tiles; one eager and one timed graph step)
+and the CPU oracle on samples (each leg can be switched off).
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: the benchmark
 measures one GPU (the scan shards by reads across GPUs with no collective).
@@ -26,10 +34,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks used for the roofline objects
+# MI355X figures used for the roofline objects
 HBM_PEAK_GBS = 8000.0
 CU, SIMD_LANES, CLOCK = 256, 64, 2.4e9          # 256 CUs x 4 SIMD16 = 64 lanes/clk/CU
 INT16_PACKED_OPS = CU * SIMD_LANES * CLOCK * 2   # 16-bit lane ops/s with packed math
+# The scan's algorithmic unit, fixed whatever kernel runs: one 16-bit lane
+# operation per cell, the Kadane step's saturating add H = max(0, H + sigma)
+# (the add and the clamp at zero are one saturating add).  The running
+# maximum and the score selection are not counted: the kernel shares them
+# between cells (one three-input minimum per two steps, the per-base score
+# pairs once per window word).
+UNIT_OPS_PER_CELL = 1.0
+# Context from the paper (Table 3(b) and its CPU comparison; rates derived
+# from the printed minutes, one strand): Tesla M2050 and 12-core Xeon X5650.
+PAPER_CONTEXT = {"gpu_gcups_derived": 69.0, "gpu": "Tesla M2050 (Fermi), MaxSSmap 28 min for "
+                 "100,000 x 251 bp reads on E. coli",
+                 "cpu_gcups_derived": 8.6, "cpu": "12-core Xeon X5650, OpenMP, 224 min"}
 
 
 def recorded_traffic(workload: str):
@@ -55,48 +75,101 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, budget_s: float = 15.0):
-    """The oracle as it stands on this host, on a bounded prefix of the
-    workload's reads (scan + NW), in GCUPS."""
+def cpu_info() -> dict:
+    """The host's CPU model, its logical CPU count, the CPUs this process may
+    run on and the cgroup CPU quota (None when unlimited)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)), "cgroup_quota_cpus": quota}
+
+
+def cpu_threads(info: dict) -> int:
+    """Threads for the all-cores leg: the CPUs this process may run on,
+    bounded by the cgroup quota and by OMP_NUM_THREADS when the host sets it
+    (the CPU share a one-GPU job is given)."""
+    n = info["affinity"]
+    if info["cgroup_quota_cpus"]:
+        n = min(n, max(1, int(info["cgroup_quota_cpus"])))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_baseline(w, budget_s: float = 6.0):
+    """The oracle as it stands on this host (scan + top-2 + NW), median of
+    three runs on each of two legs: all cores (see cpu_threads) on a sample of
+    the workload's reads sized to about budget_s, and one thread on a sample
+    sized to about budget_s / 2 per run (so at least 10 s over its three
+    runs).  The tiny workload (50 kbp, 200 reads) is timed in full; the
+    full-workload time is an extrapolation from the all-cores rate."""
     import numpy as np
 
+    import gen
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    info = cpu_info()
+    threads = cpu_threads(info)
     G = w.genome.G
-    lens = w.reads.lengths()
-    # calibrate on a few reads, then size the sample to the time budget
+
+    def run(sub, nt, ww=w):
+        t0 = time.perf_counter()
+        top = oracle.scan(ww.genome.seq, ww.F, sub.seq, sub.offsets, ww.M, ww.X, nthreads=nt)
+        oracle.align_top(ww.genome.seq, ww.F, sub.seq, sub.offsets, top, ww.pad, ww.M, ww.X,
+                         ww.gap)
+        return time.perf_counter() - t0
+
+    # calibration: one read per thread
     k0 = min(threads, w.reads.n)
-    sub = w.reads.subset(np.arange(k0))
-    t0 = time.perf_counter()
-    top = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, nthreads=threads)
-    oracle.align_top(w.genome.seq, w.F, sub.seq, sub.offsets, top, w.pad, w.M, w.X, w.gap)
-    dt0 = time.perf_counter() - t0
-    k = int(max(k0, min(w.reads.n, k0 * max(1.0, (budget_s - dt0) / max(dt0, 1e-3)))))
-    k = (k // threads) * threads or k0
-    sub = w.reads.subset(np.arange(k0, k0 + k) % w.reads.n)
-    t0 = time.perf_counter()
-    top = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, nthreads=threads)
-    oracle.align_top(w.genome.seq, w.F, sub.seq, sub.offsets, top, w.pad, w.M, w.X, w.gap)
-    dt = time.perf_counter() - t0
-    cells = 2.0 * G * float(sub.lengths().sum())
-    # one thread, on a quarter of one thread's share of the sample (about a
-    # quarter of the multi-threaded run's time)
-    k1 = max(1, int(0.25 * k / threads))
-    one = w.reads.subset(np.arange(k1))
-    t0 = time.perf_counter()
-    top = oracle.scan(w.genome.seq, w.F, one.seq, one.offsets, w.M, w.X, nthreads=1)
-    oracle.align_top(w.genome.seq, w.F, one.seq, one.offsets, top, w.pad, w.M, w.X, w.gap)
-    dt1 = time.perf_counter() - t0
-    cells1 = 2.0 * G * float(one.lengths().sum())
-    full_cells = 2.0 * G * float(lens.sum())
-    return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d of the %d reads (scan both strands + top-2 + NW), %.1f s" % (
-                k, w.reads.n, dt),
+    dt0 = run(w.reads.subset(np.arange(k0)), threads)
+    per_read_mt = dt0 / k0 * threads          # seconds per read on one of `threads` threads
+    k = int(min(w.reads.n, max(threads, budget_s / max(per_read_mt, 1e-6) * threads)))
+    k = max(threads, (k // threads) * threads)
+    rates = []
+    for rep in range(3):
+        sub = w.reads.subset((np.arange(k) + k0 + rep * k) % w.reads.n)
+        dt = run(sub, threads)
+        rates.append(2.0 * G * float(sub.lengths().sum()) / dt / 1e9)
+    k1 = max(1, int(0.5 * budget_s / max(per_read_mt, 1e-6)))
+    rates1, t1 = [], 0.0
+    for rep in range(3):
+        one = w.reads.subset((np.arange(k1) + rep * k1) % w.reads.n)
+        dt = run(one, 1)
+        t1 += dt
+        rates1.append(2.0 * G * float(one.lengths().sum()) / dt / 1e9)
+    tiny = gen.workload("tiny")
+    tiny_rates = []
+    for _ in range(3):
+        dt = run(tiny.reads, threads, tiny)
+        tiny_rates.append(2.0 * tiny.genome.G * float(tiny.reads.lengths().sum()) / dt / 1e9)
+    value = float(np.median(rates))
+    full_cells = 2.0 * G * float(w.reads.lengths().sum())
+    return {"value": round(value, 3), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": "3 runs of %d of the %d reads (scan both strands + top-2 + NW), median; "
+                      "GCUPS of the runs %s" % (k, w.reads.n, [round(x, 3) for x in rates]),
+            "host": info,
             # an extrapolation from the sample's rate, not a measurement
-            "full_workload_s_extrapolated": round(full_cells / (cells / dt), 1),
-            "single_thread": {"value": round(cells1 / dt1 / 1e9, 3), "cores": 1,
-                              "sample": "%d reads, %.1f s" % (k1, dt1)}}
+            "full_workload_s_extrapolated": round(full_cells / (value * 1e9), 1),
+            "single_thread": {"value": round(float(np.median(rates1)), 3), "cores": 1,
+                              "sample": "3 runs of %d reads, %.1f s in all, median" % (k1, t1)},
+            "tiny_workload_in_full": {"value": round(float(np.median(tiny_rates)), 3),
+                                      "cores": threads, "reads": tiny.reads.n,
+                                      "sample": "all 200 reads of the 50 kbp workload, median "
+                                                "of 3"},
+            "paper_context": PAPER_CONTEXT}
 
 
 def proposal_leg(ix, w, seq, off, top_full, stream, args):
@@ -271,6 +344,103 @@ def excl_leg(w, seq, off, top_full, full_scan_ms, stream):
     return res
 
 
+def scan_roofline(cells: float, scan_s: float, kind: int, knp: int, workload: str,
+                  measured_peak):
+    """Roofline object of the scan kernel: the fixed algorithmic unit (one
+    16-bit lane operation per cell) against the packed 16-bit VALU peak
+    derived from the chip's unit counts and clock; the kernel's own
+    instruction count per cell is reported beside it."""
+    import paper_1403_2136_amd as mx
+    achieved = UNIT_OPS_PER_CELL * cells / scan_s / 1e12
+    peak = INT16_PACKED_OPS / 1e12
+    kops = mx.KERNEL_OPS_PER_CELL[kind]
+    r = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+         "unit": "Tops/s", "frac": round(achieved / peak, 4),
+         "traffic": recorded_traffic(workload),
+         "unit_ops_per_cell": UNIT_OPS_PER_CELL,
+         "cells_per_launch": cells,
+         "kernel": {"np": knp, "variant": ["step-max", "two-step", "register-bank"][kind],
+                    "ops_per_cell": kops,
+                    "issue_frac": round(kops * cells / scan_s / 1e12 / peak, 4)}}
+    if measured_peak:
+        r["measured_peak"] = round(measured_peak / 1e12, 2)
+        r["frac_of_measured_peak"] = round(achieved / (measured_peak / 1e12), 4)
+    return r
+
+
+def batched_run(name: str, args, steps: int, dev, measured_peak, budget_s: float):
+    """The batched path on a chromosome-scale workload: one persistent scan
+    launch per mixed-length batch, replayed from a captured HIP graph, tiles
+    from the autotuner (parity-gated).  One eager step with kernel events
+    (also the warm-up), then up to `steps` graph steps, fewer when they would
+    take more than budget_s; the first graph step includes the capture."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1403_2136_amd as mx
+    t0 = time.time()
+    w = gen.workload(name)
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap)
+    n = w.reads.n
+    log("%s: genome and index %.1fs" % (name, time.time() - t0))
+    seq = torch.from_numpy(w.reads.seq).to(dev)
+    off = torch.from_numpy(w.reads.offsets.astype(np.int64)).to(dev)
+    top = torch.empty(n * 32, dtype=torch.uint8, device=dev)
+    aln = torch.empty(n * 32, dtype=torch.uint8, device=dev)
+    stride = 256
+    cig = torch.empty(n * stride, dtype=torch.uint8, device=dev)
+    cells = 2.0 * w.genome.G * float(w.reads.lengths().sum())
+    t1 = time.time()
+    sample = w.reads.subset(np.arange(0, n, max(1, n // args.tune_sample))[:args.tune_sample])
+    tune = ix.autotune(sample.seq, sample.offsets)
+    log("%s: autotune %.1fs %s" % (name, time.time() - t1, tune))
+    plan = mx.Plan(ix, capacity=n, pad=w.pad, cigar_stride=stride)
+    stream = torch.cuda.Stream()
+
+    def step(graph):
+        with torch.cuda.stream(stream):
+            plan.run(seq, off, top, aln, cig, stream=stream, graph=graph)
+
+    mx.maxss_profile_enable(True)
+    t2 = time.perf_counter()
+    step(False)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t2
+    scan_ms, scan_k = mx.maxss_profile_read("scan")
+    nw_ms, nw_k = mx.maxss_profile_read("nw")
+    other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
+    mx.maxss_profile_enable(False)
+    log("%s: eager step %.1fs, scan kernel %.1f ms" % (name, t_eager, scan_ms))
+    k = max(1, min(steps, int(budget_s / max(t_eager, 1e-3))))
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for i in range(k):
+        step(True)
+        torch.cuda.synchronize()
+        log("%s: timed graph step %d done" % (name, i))
+    dt = time.perf_counter() - t3
+    knp, kind = ix.kernel_info()
+    scan_s = scan_ms / max(scan_k, 1) / 1e3
+    res = {"workload": "%s: %d bp genome, F=%d (%d fragments), %d reads, lengths %d-%d, both "
+                       "strands, match %d mismatch %d gap %d; step = scan + top-2 + NW" % (
+                           name, w.genome.G, w.F, ix.NF, n, int(w.reads.lengths().min()),
+                           int(w.reads.lengths().max()), w.M, w.X, w.gap),
+           "gcups": round(cells / (dt / k) / 1e9, 2), "ms_per_step": round(dt / k * 1e3, 3),
+           "steps": k, "eager_step_s": round(t_eager, 3),
+           "reads_per_s": round(n / (dt / k), 1),
+           "scan_gcups_kernel": round(cells / scan_s / 1e9, 1),
+           "scan_ms_per_launch": round(scan_s * 1e3, 3),
+           "nw_ms_per_launch": round(nw_ms / max(nw_k, 1), 3),
+           "other_ms": {kk: round(v[0] / max(v[1], 1), 3) for kk, v in other.items()},
+           "step_path": "plan + hipGraph replay (capture in the first timed step), autotuned tiles",
+           "autotune": tune,
+           "roofline": scan_roofline(cells, scan_s, kind, knp, name, measured_peak)}
+    plan.close()
+    ix.close()
+    return res, w
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,7 +450,9 @@ def main():
                     choices=["tiny", "bacterial", "chromosome", "damaged"])
     ap.add_argument("--reads", type=int, default=None, help="override the read count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=6.0,
+                    help="seconds per all-cores run of the oracle (three runs; the one-thread "
+                         "runs take half as long each)")
     ap.add_argument("--no-proposal", action="store_true",
                     help="skip the learned-proposal leg (training + reads/s vs the full scan)")
     ap.add_argument("--no-qual", action="store_true",
@@ -290,6 +462,13 @@ def main():
     ap.add_argument("--no-excl", action="store_true",
                     help="skip the leg that leaves the best fragment's neighbours out of the "
                          "second-best")
+    ap.add_argument("--no-chromosome", action="store_true",
+                    help="skip the chromosome-scale batched leg of the default run")
+    ap.add_argument("--batched-budget", type=float, default=60.0,
+                    help="seconds of timed graph steps on a chromosome-scale workload (the "
+                         "step count is lowered to fit)")
+    ap.add_argument("--tune-sample", type=int, default=256,
+                    help="reads the autotuner times each tile shape on")
     ap.add_argument("--train-reads", type=int, default=200_000)
     ap.add_argument("--damaged-train-reads", type=int, default=22_000,
                     help="training + validation reads of the damaged workload's proposal leg "
@@ -324,6 +503,36 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
         return
+    measured_peak = mx.maxss_roof_int16()
+    log("measured packed 16-bit add rate: %.2f T lane-ops/s" % (measured_peak / 1e12))
+    base = {
+        "metric": "MaxSS GCUPS; reads/s, learned-proposal vs full scan at >=99% top-1 agreement",
+        "unit": "GCUPS", "n_gpus": 1, "warmup": args.warmup, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int16", "data": "synthetic"}
+
+    if args.workload in ("chromosome", "damaged"):
+        # a chromosome-scale step takes tens of seconds: the timed steps are
+        # capped to the batched budget
+        bres, w = batched_run(args.workload, args, args.steps, dev, measured_peak,
+                              args.batched_budget)
+        res = dict(base, value=bres["gcups"], steps=bres["steps"], ms_per_step=bres["ms_per_step"],
+                   config={k: v for k, v in bres.items() if k not in ("gcups", "roofline")},
+                   roofline=bres["roofline"])
+        res["config"]["steps_requested"] = args.steps
+        if not args.no_proposal and w.name == "damaged":
+            ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap)
+            seq = torch.from_numpy(w.reads.seq).to(dev)
+            off = torch.from_numpy(w.reads.offsets.astype(np.int64)).to(dev)
+            top = torch.empty(w.reads.n * 32, dtype=torch.uint8, device=dev)
+            res["proposal"] = proposal_leg(ix, w, seq, off, top, torch.cuda.current_stream(),
+                                           args)
+            ix.close()
+        if not args.no_cpu_baseline:
+            log("cpu baseline (oracle) ...")
+            res["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        print(json.dumps(res), flush=True)
+        return
+
     t0 = time.time()
     w = gen.workload(args.workload, n_reads=args.reads)
     log("workload %s: G=%d reads=%d (%.1fs)" % (w.name, w.genome.G, w.reads.n, time.time() - t0))
@@ -339,127 +548,70 @@ def main():
     G = w.genome.G
     cells = 2.0 * G * float(w.reads.lengths().sum())
 
-    batched = w.name in ("chromosome", "damaged")
-    tune = None
-    if batched:
-        # one persistent scan launch per mixed-length batch, replayed from a
-        # captured HIP graph; tiles from the autotuner (parity-gated)
-        sample = w.reads.subset(np.arange(0, n, max(1, n // 512))[:512])
-        tune = ix.autotune(sample.seq, sample.offsets)
-        log("autotune: %s" % tune)
-        plan = mx.Plan(ix, capacity=n, pad=w.pad, cigar_stride=stride)
-        stream = torch.cuda.Stream()
+    def step():
+        ix.scan(seq, off, top, stream=stream)
+        ix.align(seq, off, top, w.pad, stride, aln, cig, stream=stream)
 
-        def step(graph=True):
-            with torch.cuda.stream(stream):
-                plan.run(seq, off, top, aln, cig, stream=stream, graph=graph)
-    else:
-        def step(graph=False):
-            ix.scan(seq, off, top, stream=stream)
-            ix.align(seq, off, top, w.pad, stride, aln, cig, stream=stream)
-
-    if batched:
-        # one eager step with kernel events (graph replays carry none)
-        mx.maxss_profile_enable(True)
-        step(graph=False)
-        torch.cuda.synchronize()
-        scan_ms, scan_k = mx.maxss_profile_read("scan")
-        nw_ms, nw_k = mx.maxss_profile_read("nw")
-        other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
-        mx.maxss_profile_enable(False)
-        log("eager step: scan %.1f ms" % scan_ms)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log("warmup %d done" % i)
-    if not batched:
-        mx.maxss_profile_enable(True)
+    mx.maxss_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
-        if batched:
-            # a chromosome-scale step takes tens of seconds: wait for it and
-            # say so (microseconds against the step)
-            torch.cuda.synchronize()
-            log("timed step %d done" % i)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    if not batched:
-        scan_ms, scan_k = mx.maxss_profile_read("scan")
-        nw_ms, nw_k = mx.maxss_profile_read("nw")
-        other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
-        mx.maxss_profile_enable(False)
+    scan_ms, scan_k = mx.maxss_profile_read("scan")
+    nw_ms, nw_k = mx.maxss_profile_read("nw")
+    other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
+    mx.maxss_profile_enable(False)
     log("timed %d steps in %.3fs; scan kernel %.3f ms/launch, nw %.3f ms/launch, %s" % (
         args.steps, dt, scan_ms / max(scan_k, 1), nw_ms / max(nw_k, 1),
         {k: round(v[0] / max(v[1], 1), 3) for k, v in other.items()}))
     ms_step = dt / args.steps * 1e3
     gcups = cells / (dt / args.steps) / 1e9
     scan_s = scan_ms / max(scan_k, 1) / 1e3
-    # 16-bit lane ops per cell of the launched kernel's inner loop (score
-    # select, saturating add, running max; the library reports the variant)
     knp, kind = ix.kernel_info()
-    ops_per_cell = mx.KERNEL_OPS_PER_CELL[kind]
-    achieved = ops_per_cell * cells / scan_s / 1e12
-    peak = INT16_PACKED_OPS / 1e12
-    res = {
-        "metric": "MaxSS GCUPS; reads/s, learned-proposal vs full scan at >=99% top-1 agreement",
-        "value": round(gcups, 2),
-        "unit": "GCUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int16",
-        "data": "synthetic",
-        "config": {
-            "workload": "%s: %d bp genome, F=%d (%d fragments), %d reads, lengths %d-%d, both "
-                        "strands, match %d mismatch %d gap %d; step = scan + top-2 + NW" % (
-                            w.name, G, w.F, ix.NF, n, int(w.reads.lengths().min()),
-                            int(w.reads.lengths().max()), w.M, w.X, w.gap),
-            "reads_per_s": round(n / (dt / args.steps), 1),
-            "scan_gcups_kernel": round(cells / scan_s / 1e9, 1),
-            "scan_ms_per_launch": round(scan_s * 1e3, 3),
-            "nw_ms_per_launch": round(nw_ms / max(nw_k, 1), 3),
-            "step_path": "plan + hipGraph replay, autotuned tiles" if batched else
-                         "maxss_scan_reads + maxss_align_top",
-        },
-        "roofline": {
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": round(peak, 2),
-            "unit": "Tops/s",
-            "frac": round(achieved / peak, 4),
-            "traffic": recorded_traffic(w.name),
-            "kernel": {"np": knp, "variant": ["step-max", "two-step", "register-bank"][kind],
-                       "ops_per_cell": ops_per_cell},
-        },
+    res = dict(base, value=round(gcups, 2), steps=args.steps, ms_per_step=round(ms_step, 3))
+    res["config"] = {
+        "workload": "%s: %d bp genome, F=%d (%d fragments), %d reads, lengths %d-%d, both "
+                    "strands, match %d mismatch %d gap %d; step = scan + top-2 + NW" % (
+                        w.name, G, w.F, ix.NF, n, int(w.reads.lengths().min()),
+                        int(w.reads.lengths().max()), w.M, w.X, w.gap),
+        "reads_per_s": round(n / (dt / args.steps), 1),
+        "scan_gcups_kernel": round(cells / scan_s / 1e9, 1),
+        "scan_ms_per_launch": round(scan_s * 1e3, 3),
+        "nw_ms_per_launch": round(nw_ms / max(nw_k, 1), 3),
+        "other_ms": {k: round(v[0] / max(v[1], 1), 3) for k, v in other.items()},
+        "step_path": "maxss_scan_reads + maxss_align_top",
     }
-    if tune is not None:
-        res["config"]["autotune"] = tune
-    if not batched:
-        # PCIe-inclusive: one scan of host buffers (reads copied in, records
-        # copied out inside the call); reported beside, never as, the value
-        t0 = time.perf_counter()
-        ix.scan(w.reads.seq, w.reads.offsets)
-        t_e2e = time.perf_counter() - t0
-        res["config"]["scan_host_buffers_s"] = round(t_e2e, 3)
-        res["config"]["scan_host_buffers_gcups"] = round(cells / t_e2e / 1e9, 1)
-    if not args.no_fast and not batched:
+    res["roofline"] = scan_roofline(cells, scan_s, kind, knp, w.name, measured_peak)
+    # PCIe-inclusive: one scan of host buffers (reads copied in, records
+    # copied out inside the call); reported beside, never as, the value
+    t0 = time.perf_counter()
+    ix.scan(w.reads.seq, w.reads.offsets)
+    t_e2e = time.perf_counter() - t0
+    res["config"]["scan_host_buffers_s"] = round(t_e2e, 3)
+    res["config"]["scan_host_buffers_gcups"] = round(cells / t_e2e / 1e9, 1)
+    if not args.no_fast:
         res["fast"] = fast_leg(w, seq, off, top, scan_s * 1e3, stream)
-    if not args.no_qual and not batched:
+    if not args.no_qual:
         res["qual"] = qual_leg(w, seq, off, scan_s * 1e3, stream)
-    if not args.no_excl and not batched:
+    if not args.no_excl:
         res["exclude_adjacent"] = excl_leg(w, seq, off, top, scan_s * 1e3, stream)
-    if not args.no_proposal and w.name in ("bacterial", "damaged"):
+    if not args.no_proposal and w.name == "bacterial":
         res["proposal"] = proposal_leg(ix, w, seq, off, top, stream, args)
+    ix.close()
+    del seq, off, top, aln, cig
+    if not args.no_chromosome and w.name == "bacterial":
+        # the batched path at chromosome scale: one eager and one graph step
+        bres, _ = batched_run("chromosome", args, 1, dev, measured_peak, args.batched_budget)
+        res["chromosome"] = bres
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
-    ix.close()
     print(json.dumps(res), flush=True)
 
 

@@ -449,6 +449,15 @@ maxss_status maxss_sam_records(const maxss_reads* reads, const maxss_top2* top,
 maxss_status maxss_profile_enable(int on);
 maxss_status maxss_profile_read(const char* name, double* total_ms, uint32_t* launches);
 
+/* Measured roof of the scan's instruction class on the current device: the
+ * issue rate of packed 16-bit saturating integer adds (v_pk_add_i16), in
+ * 16-bit lane operations per second, from four launches of a kernel whose
+ * lanes each run eight independent add chains with eight waves per SIMD (the
+ * best of the last three).  The nominal figure it is set beside is CUs x 64
+ * lanes x 2 halves x clock.  Synchronous on `stream` (NULL = default);
+ * allocates a small buffer.  Errors: EINVAL (NULL), EDEVICE. */
+maxss_status maxss_roof_int16(double* ops_per_s, void* stream);
+
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char* maxss_last_error(void);
 

@@ -77,7 +77,8 @@ EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_
            "maxss_model_load", "maxss_profiles", "maxss_proposal_scores",
            "maxss_proposal_candidates", "maxss_scan_reads_proposed", "maxss_model_train_step",
            "maxss_mapq", "maxss_sam_header", "maxss_sam_records",
-           "maxss_profile_enable", "maxss_profile_read", "maxss_last_error", "maxss_version")
+           "maxss_profile_enable", "maxss_profile_read", "maxss_roof_int16", "maxss_last_error",
+           "maxss_version")
 MLP_PARAMS = 131585
 
 _lib = None
@@ -160,6 +161,8 @@ def lib():
         L.maxss_profile_enable.argtypes = [c.c_int]
         L.maxss_profile_read.restype = c.c_int
         L.maxss_profile_read.argtypes = [c.c_char_p, c.POINTER(c.c_double), c.POINTER(c.c_uint32)]
+        L.maxss_roof_int16.restype = c.c_int
+        L.maxss_roof_int16.argtypes = [c.POINTER(c.c_double), c.c_void_p]
         L.maxss_last_error.restype = c.c_char_p
         L.maxss_last_error.argtypes = []
         L.maxss_version.restype = c.c_char_p
@@ -249,6 +252,14 @@ def maxss_profile_read(name: str):
     t, k = ctypes.c_double(), ctypes.c_uint32()
     _check(lib().maxss_profile_read(name.encode(), ctypes.byref(t), ctypes.byref(k)))
     return t.value, k.value
+
+
+def maxss_roof_int16(stream=None) -> float:
+    """Measured packed 16-bit add issue rate of the current device (lane
+    operations per second)."""
+    v = ctypes.c_double()
+    _check(lib().maxss_roof_int16(ctypes.byref(v), _stream_handle(stream)))
+    return v.value
 
 
 def maxss_index_genome(seq, frag_len: int, max_read_len: int, match: int = 1,
