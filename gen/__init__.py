@@ -208,15 +208,18 @@ def chromosome_genome(seed: int, G: int = 248_000_000, gc: float = 0.41, familie
     st = Stream(seed, "genome.copies")
     target = int(repeat_frac * G)
     tot = n = 0
+    placed = []     # (position, length, family, divergence) of every copy
     while tot < target:
         fam = int(st.integers(0, families, 1)[0])
         d = float(st.uniform(1)[0]) * div_hi
         c = substitute(st, cons[fam], d)
         pos = int(st.integers(0, G - c.size + 1, 1)[0])
         seq[pos:pos + c.size] = c
+        placed.append((pos, int(c.size), fam, d))
         tot += c.size
         n += 1
-    return Genome(seq, "chromosome", dict(seed=seed, gc=gc, repeat_bases=tot, copies=n))
+    return Genome(seq, "chromosome", dict(seed=seed, gc=gc, repeat_bases=tot, copies=n,
+                                          placed=placed))
 
 
 def with_n_runs(g: Genome, seed: int, runs: int, run_lo: int = 1, run_hi: int = 200) -> Genome:

@@ -4,15 +4,16 @@ Scaled-down genomes of the same kind (41% GC, interspersed repeat families,
 F = 4096) are checked in full against the oracle, through the plan and its
 captured graph, NW included, and through the learned proposal.  The
 full-size workloads run in the launch configuration of the benchmark (one
-plan, graph replay) and are checked on sampled reads: a fragment's value
-depends only on the bases of its extended window, so the oracle runs on 16
-genome slices at once (each slice holds whole fragments plus the read-length
-extension) and the per-fragment values are stitched back together; the
-representative (strand, offset) of each reported fragment is recomputed from
-window scores.  Every read is also checked against properties that hold at
-any size.
+plan, graph replay) and are checked on sampled reads against records the
+oracle wrote (tests/golden/make_fullsize_records.py: a fragment's value
+depends only on the bases of its extended window, so the oracle runs on
+genome slices at once and the per-fragment values are stitched back
+together).  Every read is also checked against properties that hold at any
+size.
 """
-import threading
+import hashlib
+import json
+import os
 import time
 
 import numpy as np
@@ -26,6 +27,16 @@ from oracle import mlp
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("frag", "score", "offset", "strand")
+GOLDEN_FULLSIZE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "fullsize_records.json")
+
+
+def reads_sha256(r) -> str:
+    """Digest of a read set (offsets, then bases), as the golden script takes it."""
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(r.offsets, dtype=np.uint64).tobytes())
+    h.update(np.ascontiguousarray(r.seq, dtype=np.uint8).tobytes())
+    return h.hexdigest()
 
 
 def _torch():
@@ -59,74 +70,6 @@ def plan_step(ix, r, pad, stride=512, graph=True):
             aln.cpu().numpy().view(mx.ALN_DTYPE).copy(), cig.cpu().numpy())
 
 
-def _top2_from_values(v):
-    """(frag, score) pairs by (value desc, id asc) from an n x NF matrix."""
-    f1 = np.argmax(v, axis=1)
-    s1 = v[np.arange(v.shape[0]), f1]
-    w = v.astype(np.int64).copy()
-    w[np.arange(v.shape[0]), f1] = np.iinfo(np.int64).min
-    f2 = np.argmax(w, axis=1)
-    return f1, s1, f2, v[np.arange(v.shape[0]), f2]
-
-
-def _rep(genome, F, E, read, f, M, X):
-    """(score, strand, offset) of fragment f: the smallest strand, then the
-    smallest offset, among the window maxima, from the oracle's window
-    scores on the fragment's extended window."""
-    G = genome.size
-    lo, hi = f * F, min(G, f * F + F + E - 1)
-    win = genome[lo:hi].tobytes()
-    rc = oracle.revcomp(read)
-    best = (-1, 0, 0)
-    for s, q in ((0, read), (1, rc)):
-        for o in range(min(F, max(0, G - lo)) if lo < G else 0):
-            sc = oracle.window_score(q, win, o, M, X)
-            if sc > best[0]:
-                best = (sc, s, o)
-    if best[0] < 0:     # fragment wholly past the genome: every window scores 0
-        best = (0, 0, 0)
-    return best
-
-
-def oracle_sliced(genome, F, E, sub, M, X, nslices=16):
-    """Top-2 records of `sub` from the oracle run on `nslices` genome slices in
-    parallel threads (ctypes releases the interpreter lock)."""
-    G = genome.size
-    NF = (G + F - 1) // F
-    bounds = np.linspace(0, NF, nslices + 1).astype(np.int64)
-    vals = np.zeros((sub.n, NF), dtype=np.int32)
-    errors = []
-
-    def work(k):
-        try:
-            a, b = int(bounds[k]), int(bounds[k + 1])
-            if a == b:
-                return
-            lo, hi = a * F, min(G, b * F + E - 1)
-            _, v = oracle.scan(genome[lo:hi], F, sub.seq, sub.offsets, M, X, nthreads=1,
-                               want_values=True)
-            vals[:, a:b] = v[:, :b - a]
-        except Exception as e:      # re-raised below
-            errors.append(e)
-
-    th = [threading.Thread(target=work, args=(k,)) for k in range(nslices)]
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
-    assert not errors, errors
-    f1, s1, f2, s2 = _top2_from_values(vals)
-    ref = np.zeros(sub.n, dtype=mx.TOP2_DTYPE)
-    for i in range(sub.n):
-        q = sub.read(i)
-        for e, (f, s) in enumerate(((f1[i], s1[i]), (f2[i], s2[i]))):
-            sc, st, off = _rep(genome, F, E, q, int(f), M, X)
-            assert sc == s
-            ref["frag"][i][e], ref["score"][i][e] = f, s
-            ref["strand"][i][e], ref["offset"][i][e] = st, off
-    return ref
-
-
 def check_properties(w, got, aln):
     """Invariants over every read of a workload."""
     lens = w.reads.lengths().astype(np.int64)
@@ -141,24 +84,6 @@ def check_properties(w, got, aln):
     assert (got["frag"][tie, 0] < got["frag"][tie, 1]).all()
     assert (aln["strand"] == got["strand"][:, 0]).all()
     assert (aln["ref_begin"] <= aln["ref_end"]).all()
-
-
-def _sample(w, n_each, seed):
-    """Sorted read indices: `n_each` per distinct length class (five classes
-    for the length mix, else quantiles of the length range)."""
-    lens = w.reads.lengths()
-    st = gen.Stream(seed, "workload.sample")
-    classes = np.unique(lens)
-    if classes.size > 5:
-        edges = np.quantile(lens, [0, 0.5, 1])
-        classes = [classes[classes <= edges[1]], classes[classes > edges[1]]]
-    else:
-        classes = [[c] for c in classes]
-    idx = []
-    for c in classes:
-        pool = np.nonzero(np.isin(lens, c))[0]
-        idx.extend(pool[st.integers(0, pool.size, n_each)].tolist())
-    return np.unique(np.array(idx))
 
 
 # ------------------------------------------------------------ scaled down
@@ -227,31 +152,29 @@ def test_damaged_reads_plan_and_proposal(chrom_small):
     ix.close()
 
 
-def test_sliced_oracle_equals_whole_oracle(chrom_small):
-    """The slicing used for the full-size checks reproduces the plain oracle."""
-    g = chrom_small
-    r = gen.sample_reads(g, 6, 35, [36, 51, 250], 0.1, 0.3, indel_max=2)
-    whole = oracle.scan(g.seq, 4096, r.seq, r.offsets, nthreads=6)
-    assert_same(oracle_sliced(g.seq, 4096, 250, r, 1, -1, nslices=7), whole, "sliced")
-
-
 # ------------------------------------------------------------- full size
 
 @pytest.mark.slow
 @pytest.mark.parametrize("name", ["chromosome", "damaged"])
 def test_full_size_workload_sampled(name):
     """The whole workload in one plan step (graph replay); sampled reads
-    against the sliced oracle; invariants over every read."""
+    (chromosome: 10 per length class, damaged: 24; about a third of them from
+    repeat-family copies) against the oracle's records stored by
+    tests/golden/make_fullsize_records.py; invariants over every read."""
     t0 = time.time()
+    gold = json.load(open(GOLDEN_FULLSIZE))[name]
     w = gen.workload(name)
+    assert w.reads.n == gold["n_reads"] and w.genome.G == gold["G"]
+    assert reads_sha256(w.reads) == gold["reads_sha256"], "generator output changed"
     ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap)
     print("%s: genome and index %.1fs" % (name, time.time() - t0), flush=True)
     got, aln, _ = plan_step(ix, w.reads, w.pad, stride=256)
     ix.close()
     print("%s: plan step %.1fs" % (name, time.time() - t0), flush=True)
     check_properties(w, got, aln)
-    idx = _sample(w, 1 if name == "chromosome" else 3, 78)
-    sub = w.reads.subset(idx)
-    ref = oracle_sliced(w.genome.seq, w.F, w.max_read_len, sub, w.M, w.X)
-    print("%s: oracle on %d reads %.1fs" % (name, sub.n, time.time() - t0), flush=True)
+    idx = np.array(gold["index"], dtype=np.int64)
+    ref = np.zeros(idx.size, dtype=mx.TOP2_DTYPE)
+    for i, rec in enumerate(gold["records"]):
+        for f in FIELDS:
+            ref[f][i] = rec[f]
     assert_same(got[idx], ref, name + " sample")
