@@ -331,9 +331,31 @@ maxss_status maxss_index_set_tiles(maxss_index* index, int32_t np, uint32_t read
 
 typedef struct maxss_model maxss_model; /* opaque, library-owned */
 
-/* Create a model on the current device from MAXSS_MLP_PARAMS host floats
- * (fp32 master copy; Adam state zero).  Errors: EINVAL, ENOMEM, EDEVICE. */
-maxss_status maxss_model_create(const float* params, maxss_model** out);
+/* Initialisations of maxss_model_create.
+ *   MAXSS_INIT_GLOROT: W1 and w2 uniform in +-sqrt(6 / (fan_in + fan_out))
+ *     (Glorot & Bengio, 2010), biases 0.  The draws come from SplitMix64
+ *     (Steele, Lea & Flood, OOPSLA 2014) in counter mode: draw k of stream s
+ *     under `seed` is mix64(key + (k + 1) * 0x9E3779B97F4A7C15) with
+ *     key = mix64(seed * 0x9E3779B97F4A7C15 + s), mix64 the generator's
+ *     output function; a unit double is the top 53 bits times 2^-53.  W1
+ *     element i is (2u - 1) a1 with u from draw i of stream 1, w2 element k
+ *     from draw 131072 + k; computed in double, rounded to float.
+ *   MAXSS_INIT_PROFILE_MATCH: hidden unit k compares bin k of the two
+ *     profiles: W1[k][k] = 8 (read), W1[k][256 + k] = 1 (fragment), every
+ *     other weight 0, b1 = -0.2, w2 = 1, b2 = 0.  A read's 4-mers that the
+ *     fragment holds then add the fragment's share of them, which ranks
+ *     fragments much like the cosine of the two profiles; `seed` is unused. */
+#define MAXSS_INIT_GLOROT 0u
+#define MAXSS_INIT_PROFILE_MATCH 1u
+
+/* Create a model on the current device with initial parameters `init`
+ * (fp32 master copy; Adam state zero).  Errors: EINVAL (NULL, unknown init),
+ * ENOMEM, EDEVICE. */
+maxss_status maxss_model_create(uint32_t seed, uint32_t init, maxss_model** out);
+
+/* Create a model from MAXSS_MLP_PARAMS host floats instead (Adam state
+ * zero).  Errors: EINVAL, ENOMEM, EDEVICE. */
+maxss_status maxss_model_from_params(const float* params, maxss_model** out);
 void maxss_model_free(maxss_model* model);
 
 /* Copy the fp32 master parameters to `out` (host, MAXSS_MLP_PARAMS floats). */
@@ -360,14 +382,18 @@ maxss_status maxss_proposal_scores(const maxss_index* index, maxss_model* model,
  * highest scores (ties to the smaller id) are scanned exactly and the top-2
  * among them are reported; a read whose two best scores differ by less than
  * `margin` is scanned in full instead (fell_back[i] = 1; device, may be
- * NULL).  Records have the layout and tie rules of maxss_scan_reads; they
+ * NULL).  With min_score >= 0 (the exact-score guard) the candidates of
+ * every read are scanned first, and a read whose margin is below `margin`
+ * still keeps that record when its best candidate's exact MaxSS score is at
+ * least min_score; min_score < 0 turns the guard off.  Records have the layout and tie rules of maxss_scan_reads; they
  * equal the full scan's whenever its top-2 fragments are among the K.
  * With MAXSS_EXCLUDE_ADJACENT the second is the best candidate other than
  * the best one's neighbours.  Device reads.  Errors: EINVAL (K = 0 or >
  * 4096), ENOMEM, EDEVICE. */
 maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxss_model* model,
                                        const maxss_reads* reads, uint32_t K, float margin,
-                                       maxss_top2* out, uint8_t* fell_back, void* stream);
+                                       int32_t min_score, maxss_top2* out, uint8_t* fell_back,
+                                       void* stream);
 
 /* The proposal alone: per read, the K candidate fragments (device, n*K
  * int32, ascending ids; -1 past min(K, NF)), the margin between the two best
@@ -392,6 +418,74 @@ maxss_status maxss_model_train_step(maxss_model* model, const maxss_index* index
                                     const maxss_reads* batch, const int32_t* cand,
                                     const int8_t* strand, float lr, float* loss, float* grad,
                                     void* stream);
+
+/* Training on plain-scan labels, in the library.  reads: device reads;
+ * labels: their maxss_scan_reads records (device).  The first n - n_val
+ * reads train, the last n_val = floor(n * val_fraction) are held out; reads
+ * whose label is invalid are skipped.  Step t takes reads t*batch ..
+ * t*batch + batch - 1 of the concatenated epochs, epoch e ordering the
+ * training reads by (draw r of stream 16 + e, r) (SplitMix64 as for
+ * MAXSS_INIT_GLOROT, seed = opts->seed).  Each read trains on its label's
+ * strand profile against 64 candidates, the label first, then: the
+ * second-best fragment (when there is one), up to hard_negatives of the
+ * model's own best fragments other than the label (the top hard_negatives + 1
+ * by score, ascending ids, re-ranked every step), and distinct uniform draws
+ * (draw (t*batch + b)*512 + k of stream 2, f = floor(u (NF - 1)), plus 1 if
+ * f >= label) until 63 negatives are found; with fewer fragments the list is
+ * repeated.  Loss and Adam as maxss_model_train_step.  Every eval_every
+ * steps (and at the end) the held-out recall@K is measured, and the model
+ * keeps the parameters of the best one (the initial ones if no step
+ * improved it).  Then, on the held-out reads, the thresholds of
+ * maxss_scan_reads_proposed are chosen by maxss_choose_acceptance for
+ * target_agreement.  Synchronous on `stream`.  Errors: EINVAL (NULL, host
+ * reads, options out of range, no labelled training read), ESTATE (devices
+ * differ), ENOMEM, EDEVICE. */
+typedef struct {
+  uint32_t steps;          /* Adam steps (0: thresholds only)                */
+  uint32_t batch;          /* reads per step, 1..65536                       */
+  float lr;                /* Adam learning rate, >= 0                       */
+  uint32_t seed;           /* read order and negative draws                  */
+  uint32_t hard_negatives; /* 0..62                                          */
+  uint32_t eval_every;     /* steps between held-out evaluations (0: end)    */
+  uint32_t K;              /* candidates per read, 1..4096                   */
+  float val_fraction;      /* 0..0.9                                          */
+  float target_agreement;  /* held-out top-1 agreement for the thresholds    */
+  float* loss_trace;       /* host, `steps` floats (batch losses), or NULL   */
+  int32_t* cand_trace;     /* host, steps * batch * 64 ints: every step's
+                            * candidate rows (label first), or NULL; a copy
+                            * per step, for checking the draws              */
+} maxss_train_opts;
+
+typedef struct {
+  uint32_t n_train, n_val;       /* reads trained on / held out               */
+  uint32_t steps_run, best_step; /* best_step: parameters kept (0 = initial)  */
+  float loss_first, loss_last;   /* batch loss of the first and last step     */
+  float val_recall_init;         /* held-out recall@K before training         */
+  float val_recall_best;         /* and of the parameters kept (-1: no reads) */
+  float tau;                     /* margin threshold (+inf: margins accept none) */
+  int32_t min_score;             /* exact-score threshold (-1: none accepted) */
+  float val_accept;              /* held-out fraction accepted by the two     */
+  float val_agreement;           /* held-out top-1 agreement with them        */
+} maxss_train_stats;
+
+maxss_status maxss_model_train(maxss_model* model, const maxss_index* index,
+                               const maxss_reads* reads, const maxss_top2* labels,
+                               const maxss_train_opts* opts, maxss_train_stats* stats,
+                               void* stream);
+
+/* Thresholds of the proposed scan from n held-out reads (host arrays): the
+ * network's margin, the best candidate's exact score (-1 if none) and
+ * whether the best candidate is the full scan's best fragment.  A read is
+ * accepted when margin >= tau or best_score >= min_score; an accepted read
+ * agrees when `correct`, a fallen-back read always agrees.  min_score is the
+ * smallest score whose acceptance keeps the agreement >= target (-1 if even
+ * the best score would break it); then tau is the smallest margin that keeps
+ * it among the reads left (+inf if none).  accept_frac and agreement (may be
+ * NULL) report the result.  Host only.  Errors: EINVAL (NULL, target outside
+ * [0, 1]). */
+maxss_status maxss_choose_acceptance(uint32_t n, const float* margin, const int32_t* best_score,
+                                     const uint8_t* correct, float target, float* tau,
+                                     int32_t* min_score, float* accept_frac, float* agreement);
 
 /* ---------------------------------------------------------------- SAM output
  * Mapping quality and SAM records (Methods, paragraph on mapping qualities,

@@ -26,6 +26,23 @@ Definitions:
   * Proposal: s_f = max over strands of y(read strand profile, fragment f);
     order by (s desc, f asc); the K first are the candidates; margin =
     s_(1) - s_(2); a read falls back to the full scan when margin < tau.
+  * Random numbers of the training (the builder's design, stated in the
+    library's header): SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in
+    counter mode, draw k of stream s under a seed = mix64(key + (k+1) gamma),
+    key = mix64(seed gamma + s), gamma = 0x9E3779B97F4A7C15; unit double =
+    top 53 bits / 2^53; integer in [0, n) = floor(unit n).  Streams: 1
+    initial weights, 2 negatives, 16 + e read order of epoch e.
+  * Initial weights: Glorot uniform (W1 element i = (2u_i - 1) sqrt(6/768),
+    w2 element k = (2u_{131072+k} - 1) sqrt(6/257), biases 0) or the
+    profile-matching start (W1[k][k] = 8, W1[k][256+k] = 1, b1 = -0.2,
+    w2 = 1, b2 = 0).
+  * Training batches: epoch e orders the labelled training reads by (draw r
+    of stream 16+e, r); step t takes positions t B .. t B + B - 1 of the
+    epochs laid end to end.  Candidates of slot b: the label, the second
+    best (if it is another fragment), distinct uniform draws over the other
+    fragments (draw (t B + b) 512 + k of stream 2, k < 512; f = floor(u
+    (NF-1)), plus 1 when f >= label) up to 63 negatives, then the other
+    fragments in increasing order, then the negatives found repeated.
 """
 from __future__ import annotations
 
@@ -202,3 +219,96 @@ def top2_among(values: np.ndarray, cand) -> tuple:
     f1 = order[0]
     f2 = order[1] if len(order) > 1 else -1
     return f1, int(values[f1]), f2, (int(values[f2]) if f2 >= 0 else -1)
+
+
+# ----------------------------------------------------- training random numbers
+
+MASK64 = (1 << 64) - 1
+GAMMA = 0x9E3779B97F4A7C15
+
+
+def mix64(z: int) -> int:
+    """SplitMix64's output function (plain Python integers)."""
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def sm_key(seed: int, stream: int) -> int:
+    return mix64((seed * GAMMA + stream) & MASK64)
+
+
+def sm_draw(key: int, k: int) -> int:
+    return mix64((key + (k + 1) * GAMMA) & MASK64)
+
+
+def sm_unit(x: int) -> float:
+    return (x >> 11) * (1.0 / 9007199254740992.0)
+
+
+def init_params(seed: int, kind: int) -> np.ndarray:
+    """Initial parameters (float32) of the two initialisations (0 Glorot,
+    1 profile matching)."""
+    p = np.zeros(N_PARAMS, dtype=np.float32)
+    nw1 = H * 2 * D
+    if kind == 1:
+        for k in range(H):
+            p[k * 2 * D + k] = 8.0
+            p[k * 2 * D + D + k] = 1.0
+            p[nw1 + k] = -0.2
+            p[nw1 + H + k] = 1.0
+        return p
+    key = sm_key(seed, 1)
+    a1 = np.sqrt(6.0 / (2 * D + H))
+    a2 = np.sqrt(6.0 / (H + 1))
+    for i in range(nw1):
+        p[i] = np.float32((2.0 * sm_unit(sm_draw(key, i)) - 1.0) * a1)
+    for k in range(H):
+        p[nw1 + H + k] = np.float32((2.0 * sm_unit(sm_draw(key, nw1 + k)) - 1.0) * a2)
+    return p
+
+
+def epoch_order(seed: int, e: int, valid) -> list:
+    key = sm_key(seed, 16 + e)
+    return [r for _, r in sorted((sm_draw(key, r), r) for r in valid)]
+
+
+def batch_reads(seed: int, t: int, B: int, valid) -> list:
+    """Read indices of step t."""
+    out, cache = [], {}
+    for b in range(B):
+        p = t * B + b
+        e = p // len(valid)
+        if e not in cache:
+            cache[e] = epoch_order(seed, e, valid)
+        out.append(cache[e][p % len(valid)])
+    return out
+
+
+def batch_candidates(seed: int, t: int, B: int, b: int, label: int, second: int, NF: int) -> list:
+    """The 64 candidates (label first) of slot b of step t, without hard
+    negatives."""
+    row = [label]
+    if 0 <= second < NF and second != label:
+        row.append(second)
+    if NF > 1:
+        key = sm_key(seed, 2)
+        for k in range(512):
+            if len(row) == 64:
+                break
+            f = int(sm_unit(sm_draw(key, (t * B + b) * 512 + k)) * (NF - 1))
+            if f >= label:
+                f += 1
+            if f not in row:
+                row.append(f)
+    for f in range(NF):
+        if len(row) == 64:
+            break
+        if f != label and f not in row:
+            row.append(f)
+    n = len(row)
+    while len(row) < 64:
+        j = len(row)
+        row.append(row[1 + (j - n) % (n - 1)] if n > 1 else label)
+    return row

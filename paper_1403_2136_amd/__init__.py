@@ -62,6 +62,23 @@ class TuneResult(ctypes.Structure):
                 ("rejected", ctypes.c_uint32), ("from_cache", ctypes.c_uint32)]
 
 
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint32), ("hard_negatives", ctypes.c_uint32),
+                ("eval_every", ctypes.c_uint32), ("K", ctypes.c_uint32),
+                ("val_fraction", ctypes.c_float), ("target_agreement", ctypes.c_float),
+                ("loss_trace", ctypes.c_void_p), ("cand_trace", ctypes.c_void_p)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("n_train", ctypes.c_uint32), ("n_val", ctypes.c_uint32),
+                ("steps_run", ctypes.c_uint32), ("best_step", ctypes.c_uint32),
+                ("loss_first", ctypes.c_float), ("loss_last", ctypes.c_float),
+                ("val_recall_init", ctypes.c_float), ("val_recall_best", ctypes.c_float),
+                ("tau", ctypes.c_float), ("min_score", ctypes.c_int32),
+                ("val_accept", ctypes.c_float), ("val_agreement", ctypes.c_float)]
+
+
 class Reads(ctypes.Structure):
     _fields_ = [("seq", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_uint32),
                 ("on_device", ctypes.c_uint32), ("qual", ctypes.c_void_p)]
@@ -73,13 +90,16 @@ EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_
            "maxss_align_top", "maxss_plan_create", "maxss_plan_free", "maxss_plan_run",
            "maxss_plan_run_graph", "maxss_autotune", "maxss_index_set_tiles",
            "maxss_scan_kernel_info",
-           "maxss_model_create", "maxss_model_free", "maxss_model_get_params", "maxss_model_save",
+           "maxss_model_create", "maxss_model_from_params", "maxss_model_free",
+           "maxss_model_get_params", "maxss_model_save",
            "maxss_model_load", "maxss_profiles", "maxss_proposal_scores",
            "maxss_proposal_candidates", "maxss_scan_reads_proposed", "maxss_model_train_step",
+           "maxss_model_train", "maxss_choose_acceptance",
            "maxss_mapq", "maxss_sam_header", "maxss_sam_records",
            "maxss_profile_enable", "maxss_profile_read", "maxss_roof_int16", "maxss_last_error",
            "maxss_version")
 MLP_PARAMS = 131585
+MAXSS_INIT_GLOROT, MAXSS_INIT_PROFILE_MATCH = 0, 1
 
 _lib = None
 
@@ -130,7 +150,17 @@ def lib():
         L.maxss_scan_kernel_info.restype = c.c_int
         L.maxss_scan_kernel_info.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p]
         L.maxss_model_create.restype = c.c_int
-        L.maxss_model_create.argtypes = [c.c_void_p, c.POINTER(c.c_void_p)]
+        L.maxss_model_create.argtypes = [c.c_uint32, c.c_uint32, c.POINTER(c.c_void_p)]
+        L.maxss_model_from_params.restype = c.c_int
+        L.maxss_model_from_params.argtypes = [c.c_void_p, c.POINTER(c.c_void_p)]
+        L.maxss_model_train.restype = c.c_int
+        L.maxss_model_train.argtypes = [c.c_void_p, c.c_void_p, c.POINTER(Reads), c.c_void_p,
+                                        c.POINTER(TrainOpts), c.POINTER(TrainStats), c.c_void_p]
+        L.maxss_choose_acceptance.restype = c.c_int
+        L.maxss_choose_acceptance.argtypes = [c.c_uint32, c.c_void_p, c.c_void_p, c.c_void_p,
+                                              c.c_float, c.POINTER(c.c_float),
+                                              c.POINTER(c.c_int32), c.POINTER(c.c_float),
+                                              c.POINTER(c.c_float)]
         L.maxss_model_free.restype = None
         L.maxss_model_free.argtypes = [c.c_void_p]
         L.maxss_model_get_params.restype = c.c_int
@@ -151,8 +181,8 @@ def lib():
                                                 c.c_void_p, c.c_void_p]
         L.maxss_scan_reads_proposed.restype = c.c_int
         L.maxss_scan_reads_proposed.argtypes = [c.c_void_p, c.c_void_p, c.POINTER(Reads),
-                                                c.c_uint32, c.c_float, c.c_void_p, c.c_void_p,
-                                                c.c_void_p]
+                                                c.c_uint32, c.c_float, c.c_int32, c.c_void_p,
+                                                c.c_void_p, c.c_void_p]
         L.maxss_model_train_step.restype = c.c_int
         L.maxss_model_train_step.argtypes = [c.c_void_p, c.c_void_p, c.POINTER(Reads), c.c_void_p,
                                              c.c_void_p, c.c_float, c.c_void_p, c.c_void_p,
@@ -517,19 +547,50 @@ class Plan:
 
 
 class Model:
-    """Owner of a proposal network (fp32 master + bf16 copies + Adam state)."""
+    """Owner of a proposal network (fp32 master + bf16 copies + Adam state):
+    created in the library from a seed and an initialisation, from given
+    parameters, or loaded from a file."""
 
-    def __init__(self, params=None, path: str | None = None):
+    def __init__(self, params=None, path: str | None = None, seed: int = 0,
+                 init: int = MAXSS_INIT_GLOROT):
         h = ctypes.c_void_p()
         if path is not None:
             _check(lib().maxss_model_load(path.encode(), ctypes.byref(h)))
-        else:
+        elif params is not None:
             p = np.ascontiguousarray(params, dtype=np.float32)
             if p.size != MLP_PARAMS:
                 raise ValueError("expected %d parameters" % MLP_PARAMS)
             self._init = p
-            _check(lib().maxss_model_create(p.ctypes.data, ctypes.byref(h)))
+            _check(lib().maxss_model_from_params(p.ctypes.data, ctypes.byref(h)))
+        else:
+            _check(lib().maxss_model_create(seed, init, ctypes.byref(h)))
         self.handle = h.value
+
+    def train(self, index, seq, offsets, labels, steps: int, batch: int = 256, lr: float = 1e-3,
+              seed: int = 0, hard_negatives: int = 0, eval_every: int = 0, K: int = 64,
+              val_fraction: float = 0.1, target_agreement: float = 0.995, loss_trace=None,
+              cand_trace=None, stream=None, qual=None) -> dict:
+        """maxss_model_train on device reads and their device top-2 records;
+        returns the statistics as a dict.  loss_trace (float32, `steps`) and
+        cand_trace (int32, steps*batch*64), host numpy arrays, are filled
+        when given."""
+        r = _reads_struct(seq, offsets, True, qual)
+        tr = ct = None
+        if loss_trace is not None:
+            if not (isinstance(loss_trace, np.ndarray) and loss_trace.dtype == np.float32):
+                raise ValueError("loss_trace must be a float32 numpy array")
+            tr = _buf(loss_trace, 4 * steps, "loss_trace")
+        if cand_trace is not None:
+            if not (isinstance(cand_trace, np.ndarray) and cand_trace.dtype == np.int32):
+                raise ValueError("cand_trace must be an int32 numpy array")
+            ct = _buf(cand_trace, 4 * steps * batch * 64, "cand_trace")
+        o = TrainOpts(steps, batch, lr, seed, hard_negatives, eval_every, K, val_fraction,
+                      target_agreement, tr, ct)
+        st = TrainStats()
+        _check(lib().maxss_model_train(self.handle, h_(index), ctypes.byref(r),
+                                       _buf(labels, 32 * r.n, "labels"), ctypes.byref(o),
+                                       ctypes.byref(st), _stream_handle(stream)))
+        return {f: getattr(st, f) for f, _ in TrainStats._fields_}
 
     def params(self) -> np.ndarray:
         out = np.zeros(MLP_PARAMS, dtype=np.float32)
@@ -554,10 +615,11 @@ class Model:
                                                _buf(fell_back, r.n, "fell_back"),
                                                _stream_handle(stream)))
 
-    def scan(self, index, seq, offsets, K, margin, out, fell_back=None, stream=None, qual=None):
+    def scan(self, index, seq, offsets, K, margin, out, fell_back=None, stream=None, qual=None,
+             min_score: int = -1):
         r = _reads_struct(seq, offsets, True, qual)
         _check(lib().maxss_scan_reads_proposed(h_(index), self.handle, ctypes.byref(r), K, margin,
-                                               _buf(out, 32 * r.n, "out"),
+                                               min_score, _buf(out, 32 * r.n, "out"),
                                                _buf(fell_back, r.n, "fell_back", optional=True),
                                                _stream_handle(stream)))
 
@@ -581,6 +643,21 @@ class Model:
             self.close()
         except Exception:
             pass
+
+
+def maxss_choose_acceptance(margin, best_score, correct, target: float):
+    """(tau, min_score, accept_frac, agreement) from held-out host arrays."""
+    m = np.ascontiguousarray(margin, dtype=np.float32)
+    b = np.ascontiguousarray(best_score, dtype=np.int32)
+    c = np.ascontiguousarray(correct, dtype=np.uint8)
+    if not (m.size == b.size == c.size):
+        raise ValueError("margin, best_score and correct need one entry per read")
+    tau, ms = ctypes.c_float(), ctypes.c_int32()
+    acc, agr = ctypes.c_float(), ctypes.c_float()
+    _check(lib().maxss_choose_acceptance(m.size, m.ctypes.data, b.ctypes.data, c.ctypes.data,
+                                         target, ctypes.byref(tau), ctypes.byref(ms),
+                                         ctypes.byref(acc), ctypes.byref(agr)))
+    return tau.value, ms.value, acc.value, agr.value
 
 
 def maxss_profiles(index, seq=None, offsets=None, read_prof=None, frag_prof=None, stream=None):

@@ -26,7 +26,31 @@ static constexpr uint32_t kW1 = kH * 2 * kD;         // 131,072
 static constexpr uint32_t kParams = kW1 + kH + kH + 1;  // 131,585
 static constexpr int kCand = 64;                     // candidates per training read
 
-typedef short s16x4 __attribute__((ext_vector_type(4)));
+// SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014) in counter mode, for the random numbers the
+// library draws itself (initial weights, read order and negatives of
+// training): draw k (k = 0, 1, ...) of stream s under `seed` is
+// mix64(key + (k + 1) * gamma) with key = mix64(seed * gamma + s), mix64
+// being the generator's output function.  A unit double takes the top 53
+// bits; an integer in [0, n) is floor(unit * n).
+static constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm_key(uint64_t seed, uint64_t stream) {
+  return mix64(seed * kGamma + stream);
+}
+__host__ __device__ inline uint64_t sm_draw(uint64_t key, uint64_t k) {
+  return mix64(key + (k + 1) * kGamma);
+}
+__host__ __device__ inline double sm_unit(uint64_t x) {
+  return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+// streams: initial weights, negatives, read order of epoch e (kStreamOrder + e)
+static constexpr uint64_t kStreamInit = 1, kStreamNeg = 2, kStreamOrder = 16;
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __host__ inline uint16_t f2bf(float x) {
@@ -116,18 +140,53 @@ __device__ inline uint16_t opnd_at(const Opnd& o, int r, int k) {
   return o.p[rr * o.sr + kk * o.sk];
 }
 
+// LDS row of a staged slab: 32 k values plus 8 halfwords of padding (80
+// bytes, so 16-byte reads stay aligned and rows start on different banks).
+static constexpr int kLdsRow = 40;
+
 // One operand's 64 x 32 slab (rows base.., k k0..) into LDS, zero outside
-// [0, lim) x [k0, kend).  Consecutive threads take consecutive elements along
-// the operand's contiguous dimension, so rows of a row-major operand and
-// columns of a transposed one are both read as whole cache lines.
-__device__ inline void stage_opnd(uint16_t (*S)[36], const Opnd& o, int base, int lim, int k0,
+// [0, lim) x [k0, kend).  When the operand's k values are contiguous (row
+// gathers allowed), a thread moves 8 of them of one row with one 16-byte
+// load and store; when its rows are contiguous (reduction-index gathers
+// allowed), a thread loads 8 rows of one k value with one 16-byte load and
+// spreads them over the slab's rows; any other view, a ragged edge or an
+// unaligned address takes the element-wise path.
+__device__ inline void stage_opnd(uint16_t (*S)[kLdsRow], const Opnd& o, int base, int lim, int k0,
                                   int kend, int tid) {
-  if (o.sr == 1) {
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int r = e & 63, kk = e >> 6;
-      const int gr = base + r, gk = k0 + kk;
-      S[r][kk] = (gr < lim && gk < kend) ? opnd_at(o, gr, gk) : (uint16_t)0;
+  if (o.sk == 1 && !o.ki) {
+    const int r = tid >> 2, c = (tid & 3) * 8;
+    const int gr = base + r, gk = k0 + c;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (gr < lim) {
+      const long long rr = o.ri ? o.ri[gr] : gr;
+      const uint16_t* p = o.p + rr * o.sr + gk;
+      if (gk + 8 <= kend && (reinterpret_cast<uintptr_t>(p) & 15u) == 0) {
+        v = *reinterpret_cast<const uint4*>(p);
+      } else {
+        uint16_t h[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) h[j] = gk + j < kend ? p[j] : (uint16_t)0;
+        memcpy(&v, h, 16);
+      }
     }
+    *reinterpret_cast<uint4*>(&S[r][c]) = v;
+  } else if (o.sr == 1 && !o.ri) {
+    const int kk = tid >> 3, r = (tid & 7) * 8;
+    const int gk = k0 + kk, gr = base + r;
+    uint16_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (gk < kend) {
+      const long long kx = o.ki ? o.ki[gk] : gk;
+      const uint16_t* p = o.p + gr + kx * o.sk;
+      if (gr + 8 <= lim && (reinterpret_cast<uintptr_t>(p) & 15u) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        memcpy(h, &v, 16);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; j++) h[j] = gr + j < lim ? p[j] : (uint16_t)0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) S[r + j][kk] = h[j];
   } else {
     for (int e = tid; e < 64 * 32; e += 256) {
       const int r = e >> 5, kk = e & 31;
@@ -137,18 +196,22 @@ __device__ inline void stage_opnd(uint16_t (*S)[36], const Opnd& o, int base, in
   }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 // C[i][j] (+)= sum_k A(i,k) B(j,k) (+ bias[j]), fp32 out (ldc), bf16 in.
 // 256 threads, 64x64 output tile, each wave a 32x32 quarter of 2x2
-// v_mfma_f32_16x16x16_bf16 tiles; K staged through LDS 32 at a time.
-// blockIdx.z takes the k range [z*kchunk, (z+1)*kchunk) and writes its
-// partial product at C + z*zstride (split K).
+// v_mfma_f32_16x16x32_bf16 tiles (gfx950: lane l holds 8 consecutive k of
+// row l % 16 at k offset 8 (l / 16), one 16-byte LDS read per operand
+// tile); K staged through LDS 32 at a time.  blockIdx.z takes the k range
+// [z*kchunk, (z+1)*kchunk) and writes its partial product at C + z*zstride
+// (split K).
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, int kchunk, Opnd A,
                                                         Opnd B, float* __restrict__ C,
                                                         long long ldc, long long zstride,
                                                         const float* __restrict__ bias,
                                                         int accumulate) {
-  __shared__ uint16_t As[64][36];
-  __shared__ uint16_t Bs[64][36];
+  __shared__ __attribute__((aligned(16))) uint16_t As[64][kLdsRow];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64][kLdsRow];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
@@ -157,27 +220,22 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, int
   f32x4 acc[2][2];
   for (int a = 0; a < 2; a++)
     for (int b = 0; b < 2; b++) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const int ak = (lane >> 4) * 8;
   for (int k0 = kbeg; k0 < kend; k0 += 32) {
     stage_opnd(As, A, i0, M, k0, kend, tid);
     stage_opnd(Bs, B, j0, N, k0, kend, tid);
     __syncthreads();
+    bf16x8 a[2], b[2];
 #pragma unroll
-    for (int kk = 0; kk < 32; kk += 16) {
-      const int ak = kk + (lane >> 4) * 4;
-#pragma unroll
-      for (int ti = 0; ti < 2; ti++) {
-        const int ar = wi + ti * 16 + (lane & 15);
-        const s16x4 a = {(short)As[ar][ak], (short)As[ar][ak + 1], (short)As[ar][ak + 2],
-                         (short)As[ar][ak + 3]};
-#pragma unroll
-        for (int tj = 0; tj < 2; tj++) {
-          const int bc = wj + tj * 16 + (lane & 15);
-          const s16x4 b = {(short)Bs[bc][ak], (short)Bs[bc][ak + 1], (short)Bs[bc][ak + 2],
-                           (short)Bs[bc][ak + 3]};
-          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[ti][tj], 0, 0, 0);
-        }
-      }
+    for (int t = 0; t < 2; t++) {
+      a[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&As[wi + t * 16 + (lane & 15)][ak]));
+      b[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bs[wj + t * 16 + (lane & 15)][ak]));
     }
+#pragma unroll
+    for (int ti = 0; ti < 2; ti++)
+#pragma unroll
+      for (int tj = 0; tj < 2; tj++)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
@@ -406,6 +464,18 @@ __global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ S, 
     __syncthreads();
   }
   for (uint32_t c = Ke + tid; c < K; c += 256) out[c] = -1;
+}
+
+// fb[i] = 0 (keep the candidate scan's record) when the network's margin
+// reaches tau or the best candidate's exact score reaches min_score, else 1
+// (full scan); invalid reads keep fb = 0.
+__global__ void guard_kernel(const float* __restrict__ margin, const maxss_top2* __restrict__ oc,
+                             const uint32_t* __restrict__ lens, float tau, int32_t min_score,
+                             uint32_t n, uint8_t* __restrict__ fb) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool accept = margin[i] >= tau || oc[i].score[0] >= min_score;
+  fb[i] = (lens[i] != 0 && !accept) ? 1 : 0;
 }
 
 // lens_out[i] = (fb[i] == want) ? lens[i] : 0
@@ -660,36 +730,6 @@ static maxss_status ensure_train_scratch(Model* m, const Index* ix, uint32_t nb)
 
 using namespace maxss;
 
-extern "C" maxss_status maxss_model_create(const float* params, maxss_model** out) {
-  clear_error();
-  if (!params || !out) return fail(MAXSS_EINVAL, "NULL argument");
-  Model* m = new (std::nothrow) Model();
-  if (!m) return fail(MAXSS_ENOMEM, "host allocation");
-  maxss_status s;
-  do {
-    if ((s = check_hip(hipGetDevice(&m->device), "hipGetDevice"))) break;
-    if ((s = check_hip(hipMalloc((void**)&m->master, 4ull * kParams), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->adam_m, 4ull * kParams), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->adam_v, 4ull * kParams), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->W1a, 2ull * kH * kD), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->W1b, 2ull * kH * kD), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->w2f, 4ull * kH), "alloc")))
-      break;
-    if ((s = check_hip(hipMemcpy(m->master, params, 4ull * kParams, hipMemcpyHostToDevice), "copy")) ||
-        (s = check_hip(hipMemset(m->adam_m, 0, 4ull * kParams), "memset")) ||
-        (s = check_hip(hipMemset(m->adam_v, 0, 4ull * kParams), "memset")))
-      break;
-    if ((s = refresh_shadow(m, nullptr))) break;
-    if ((s = check_hip(hipDeviceSynchronize(), "sync"))) break;
-  } while (0);
-  if (s) {
-    maxss_model_free(reinterpret_cast<maxss_model*>(m));
-    return s;
-  }
-  *out = reinterpret_cast<maxss_model*>(m);
-  return MAXSS_OK;
-}
-
 extern "C" void maxss_model_free(maxss_model* model) {
   Model* m = reinterpret_cast<Model*>(model);
   if (!m) return;
@@ -743,7 +783,7 @@ extern "C" maxss_status maxss_model_load(const char* path, maxss_model** out) {
                   hdr[0] == 1u && hdr[2] == kParams && fread(buf.data(), 4, buf.size(), f) == buf.size();
   fclose(f);
   if (!ok) return fail(MAXSS_EINVAL, "%s is not a version-1 model file", path);
-  maxss_status s = maxss_model_create(buf.data(), out);
+  maxss_status s = maxss_model_from_params(buf.data(), out);
   if (s) return s;
   Model* m = reinterpret_cast<Model*>(*out);
   m->step = hdr[1];
@@ -948,8 +988,9 @@ extern "C" maxss_status maxss_proposal_candidates(const maxss_index* index, maxs
 
 extern "C" maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxss_model* model,
                                                   const maxss_reads* reads, uint32_t K,
-                                                  float margin_tau, maxss_top2* out,
-                                                  uint8_t* fell_back, void* stream) {
+                                                  float margin_tau, int32_t min_score,
+                                                  maxss_top2* out, uint8_t* fell_back,
+                                                  void* stream) {
   clear_error();
   const Index* ix = reinterpret_cast<const Index*>(index);
   Model* m = reinterpret_cast<Model*>(model);
@@ -986,12 +1027,22 @@ extern "C" maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxs
         (s = check_hip(hipMallocAsync((void**)&of, sizeof(maxss_top2) * n, st), "alloc")))
       break;
     if ((s = propose_impl(ix, m, wf.er, n, K, margin_tau, cand, mg, fb, st))) break;
-    mask_lens_kernel<<<(n + 255) / 256, 256, 0, st>>>(wf.er.lens, fb, 0, n, lens_c);
-    mask_lens_kernel<<<(n + 255) / 256, 256, 0, st>>>(wf.er.lens, fb, 1, n, lens_f);
-    if ((s = check_hip(hipGetLastError(), "mask_lens_kernel"))) break;
-    // candidate scan of the reads that kept their proposal
     if ((s = alloc_scan_work(ix, n, (uint64_t)n * (Kc < 16 ? Kc : 16), true, st, &wc))) break;
-    if ((s = candidate_scan(ix, wf.er, lens_c, n, cand, K, Kc, oc, wc, st))) break;
+    if (min_score >= 0) {
+      // exact-score guard: every read's candidates are scanned, and a read
+      // keeps that record when its margin reaches tau or its best
+      // candidate's exact score reaches min_score
+      if ((s = candidate_scan(ix, wf.er, wf.er.lens, n, cand, K, Kc, oc, wc, st))) break;
+      guard_kernel<<<(n + 255) / 256, 256, 0, st>>>(mg, oc, wf.er.lens, margin_tau, min_score, n, fb);
+      mask_lens_kernel<<<(n + 255) / 256, 256, 0, st>>>(wf.er.lens, fb, 1, n, lens_f);
+      if ((s = check_hip(hipGetLastError(), "guard_kernel"))) break;
+    } else {
+      mask_lens_kernel<<<(n + 255) / 256, 256, 0, st>>>(wf.er.lens, fb, 0, n, lens_c);
+      mask_lens_kernel<<<(n + 255) / 256, 256, 0, st>>>(wf.er.lens, fb, 1, n, lens_f);
+      if ((s = check_hip(hipGetLastError(), "mask_lens_kernel"))) break;
+      // candidate scan of the reads that kept their proposal
+      if ((s = candidate_scan(ix, wf.er, lens_c, n, cand, K, Kc, oc, wc, st))) break;
+    }
     // full scan of the reads that fell back
     if ((s = scan_pipeline_lens(ix, wf.er, lens_f, n, of, wf, st))) break;
     select_kernel<<<(n + 255) / 256, 256, 0, st>>>(oc, of, fb, wf.er.lens, n, out);
@@ -1007,6 +1058,68 @@ extern "C" maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxs
   release_scan_work(&wf, true, st);
   return s;
 }
+
+namespace maxss {
+
+// One step on nb reads whose label-strand profiles are rows rsel[b] of
+// `rprof` (bf16, [rows][kD]) and whose 64 candidates (label first) are
+// cand[b*64 ..]: forward, loss, backward, and with lr > 0 an Adam step.
+// loss (device float, may be NULL) gets the batch mean, grad_out (device,
+// may be NULL) the gradient.
+static maxss_status train_step_impl(Model* m, const Index* ix, const uint16_t* rprof,
+                                    const int32_t* rsel, const int32_t* cand, uint32_t nb,
+                                    float lr, float* loss, float* grad_out, hipStream_t st) {
+  maxss_status s;
+  const uint32_t P = nb * kCand;
+  // forward: A = Vr W1a^T + b1 (label strand rows), Bc = Vc W1b^T
+  {
+    Opnd a{rprof, kD, 1, rsel, nullptr};
+    Opnd b{m->W1a, kD, 1, nullptr, nullptr};
+    if ((s = gemm((int)nb, kH, kD, a, b, m->Ar, kH, m->master + kW1, false, st))) return s;
+  }
+  {
+    Opnd a{m->fprof, kD, 1, cand, nullptr};
+    Opnd b{m->W1b, kD, 1, nullptr, nullptr};
+    if ((s = gemm((int)P, kH, kD, a, b, m->Bc, kH, nullptr, false, st))) return s;
+  }
+  const float b2 = host_b2(m);
+  train_fwd_kernel<<<nb, 256, 0, st>>>(m->Ar, m->Bc, m->w2f, b2, nb, m->dy, m->lossv);
+  train_bwd_kernel<<<nb, kH, 0, st>>>(m->Ar, m->Bc, m->w2f, m->dy, m->dH, m->dA, m->part);
+  if ((s = check_hip(hipGetLastError(), "train fwd/bwd"))) return s;
+  float* tmp = m->grad + kParams;  // [2][kH][kD] fp32 for dW1a, dW1b
+  float* split = tmp + 2 * kH * kD;  // split-K partials, [kSplitMax][kH][kD]
+  {
+    // dW1a[k][j] = sum_b dA[b][k] Vr[rsel[b]][j]
+    Opnd a{m->dA, 1, kH, nullptr, nullptr};
+    Opnd b{rprof, 1, kD, nullptr, rsel};
+    if ((s = gemm(kH, kD, (int)nb, a, b, tmp, kD, nullptr, false, st, split))) return s;
+  }
+  {
+    // dW1b[k][j] = sum_p dH[p][k] Vf[cand[p]][j]
+    Opnd a{m->dH, 1, kH, nullptr, nullptr};
+    Opnd b{m->fprof, 1, kD, nullptr, cand};
+    if ((s = gemm(kH, kD, (int)P, a, b, tmp + kH * kD, kD, nullptr, false, st, split)))
+      return s;
+  }
+  assemble_w1_kernel<<<(kW1 + 255) / 256, 256, 0, st>>>(tmp, m->grad);
+  train_reduce_kernel<<<(2 * kH + 2 + 255) / 256, 256, 0, st>>>(m->part, m->lossv, nb, m->grad, loss);
+  if ((s = check_hip(hipGetLastError(), "train reduce"))) return s;
+  if (grad_out &&
+      (s = check_hip(hipMemcpyAsync(grad_out, m->grad, 4ull * kParams, hipMemcpyDeviceToDevice, st),
+                     "copy grad")))
+    return s;
+  if (lr > 0.f) {
+    m->step++;
+    const float b1c = 1.f - powf(0.9f, (float)m->step), b2c = 1.f - powf(0.999f, (float)m->step);
+    adam_kernel<<<(kParams + 255) / 256, 256, 0, st>>>(m->master, m->adam_m, m->adam_v, m->grad,
+                                                       kParams, lr, 0.9f, 0.999f, 1e-8f, b1c, b2c);
+    if ((s = check_hip(hipGetLastError(), "adam_kernel"))) return s;
+    if ((s = refresh_shadow(m, st))) return s;
+  }
+  return MAXSS_OK;
+}
+
+}  // namespace maxss
 
 extern "C" maxss_status maxss_model_train_step(maxss_model* model, const maxss_index* index,
                                                const maxss_reads* batch, const int32_t* cand,
@@ -1043,51 +1156,490 @@ extern "C" maxss_status maxss_model_train_step(maxss_model* model, const maxss_i
                                                     nullptr, 0, 0, m->rprof, nullptr);
   rsel_kernel<<<(nb + 255) / 256, 256, 0, st>>>(strand, nb, m->rsel);
   if ((s = check_hip(hipGetLastError(), "profile/rsel"))) return s;
-  const uint32_t P = nb * kCand;
-  // forward: A = Vr W1a^T + b1 (label strand rows), Bc = Vc W1b^T
-  {
-    Opnd a{m->rprof, kD, 1, m->rsel, nullptr};
-    Opnd b{m->W1a, kD, 1, nullptr, nullptr};
-    if ((s = gemm((int)nb, kH, kD, a, b, m->Ar, kH, m->master + kW1, false, st))) return s;
+  return train_step_impl(m, ix, m->rprof, m->rsel, cand, nb, lr, loss, grad_out, st);
+}
+
+// ------------------------------------------------- training loop, thresholds
+
+namespace maxss {
+
+// Initial parameters (fp32): MAXSS_INIT_GLOROT draws W1 and w2 uniformly in
+// +-sqrt(6 / (fan_in + fan_out)) (Glorot & Bengio, 2010) from stream
+// kStreamInit (W1 element i is draw i, w2 element k draw kW1 + k), biases 0.
+// MAXSS_INIT_PROFILE_MATCH sets hidden unit k to compare bin k of the two
+// profiles: W1[k][k] = 8 (read), W1[k][256 + k] = 1 (fragment), every other
+// weight 0, b1 = -0.2, w2 = 1, b2 = 0, so that a read's 4-mers present in
+// the fragment add the fragment's share of them (the score then ranks
+// fragments much like the cosine of the profiles) and training starts there.
+static void init_params(uint32_t seed, uint32_t kind, std::vector<float>& p) {
+  p.assign(kParams, 0.0f);
+  if (kind == MAXSS_INIT_PROFILE_MATCH) {
+    for (int k = 0; k < kH; k++) {
+      p[(size_t)k * 2 * kD + k] = 8.0f;
+      p[(size_t)k * 2 * kD + kD + k] = 1.0f;
+      p[kW1 + k] = -0.2f;
+      p[kW1 + kH + k] = 1.0f;
+    }
+    return;
   }
-  {
-    Opnd a{m->fprof, kD, 1, cand, nullptr};
-    Opnd b{m->W1b, kD, 1, nullptr, nullptr};
-    if ((s = gemm((int)P, kH, kD, a, b, m->Bc, kH, nullptr, false, st))) return s;
+  const uint64_t key = sm_key(seed, kStreamInit);
+  const double a1 = sqrt(6.0 / (2 * kD + kH)), a2 = sqrt(6.0 / (kH + 1));
+  for (uint32_t i = 0; i < kW1; i++) p[i] = (float)((2.0 * sm_unit(sm_draw(key, i)) - 1.0) * a1);
+  for (uint32_t k = 0; k < (uint32_t)kH; k++)
+    p[kW1 + kH + k] = (float)((2.0 * sm_unit(sm_draw(key, kW1 + k)) - 1.0) * a2);
+}
+
+// Candidate rows of a training batch: row b = [label, second (if it is a
+// fragment other than the label), hard negatives (the model's best
+// fragments other than the label, ascending ids, at most `hard`), distinct
+// uniform draws over the fragments other than the label (draw c = (t*B + b)
+// * 512 + k of stream kStreamNeg for k = 0, 1, ..., 511; f = floor(u *
+// (NF - 1)), then f + 1 if f >= label)], and, when fewer than 63 negatives
+// were found, the remaining fragments other than the label in increasing id
+// order, repeated as needed.  rsel[b] = 2 * read + label strand.
+__global__ void negatives_kernel(const int32_t* __restrict__ bidx, const maxss_top2* __restrict__ labels,
+                                 const int32_t* __restrict__ hardc, uint32_t hard_k,
+                                 uint32_t hard, uint64_t key, uint64_t t, uint32_t B,
+                                 uint32_t NF, int32_t* __restrict__ cand,
+                                 int32_t* __restrict__ rsel) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int32_t r = bidx[b];
+  const int32_t L = labels[r].frag[0], S2 = labels[r].frag[1];
+  int32_t* row = cand + (uint64_t)b * kCand;
+  rsel[b] = 2 * r + (labels[r].strand[0] ? 1 : 0);
+  row[0] = L;
+  int n = 1;
+  auto seen = [&](int32_t f) {
+    for (int j = 0; j < n; j++)
+      if (row[j] == f) return true;
+    return false;
+  };
+  if (S2 >= 0 && (uint32_t)S2 < NF && S2 != L) row[n++] = S2;
+  if (hardc) {
+    uint32_t taken = 0;
+    for (uint32_t j = 0; j < hard_k && taken < hard && n < kCand; j++) {
+      const int32_t f = hardc[(uint64_t)b * hard_k + j];
+      if (f < 0 || f == L || seen(f)) continue;
+      row[n++] = f;
+      taken++;
+    }
   }
-  const float b2 = host_b2(m);
-  train_fwd_kernel<<<nb, 256, 0, st>>>(m->Ar, m->Bc, m->w2f, b2, nb, m->dy, m->lossv);
-  train_bwd_kernel<<<nb, kH, 0, st>>>(m->Ar, m->Bc, m->w2f, m->dy, m->dH, m->dA, m->part);
-  if ((s = check_hip(hipGetLastError(), "train fwd/bwd"))) return s;
-  float* tmp = m->grad + kParams;  // [2][kH][kD] fp32 for dW1a, dW1b
-  float* split = tmp + 2 * kH * kD;  // split-K partials, [kSplitMax][kH][kD]
-  {
-    // dW1a[k][j] = sum_b dA[b][k] Vr[rsel[b]][j]
-    Opnd a{m->dA, 1, kH, nullptr, nullptr};
-    Opnd b{m->rprof, 1, kD, nullptr, m->rsel};
-    if ((s = gemm(kH, kD, (int)nb, a, b, tmp, kD, nullptr, false, st, split))) return s;
+  if (NF > 1) {
+    const uint64_t c0 = (t * B + b) * 512ull;
+    for (uint32_t k = 0; k < 512 && n < kCand; k++) {
+      int32_t f = (int32_t)(sm_unit(sm_draw(key, c0 + k)) * (double)(NF - 1));
+      if (f >= L) f++;
+      if (!seen(f)) row[n++] = f;
+    }
   }
-  {
-    // dW1b[k][j] = sum_p dH[p][k] Vf[cand[p]][j]
-    Opnd a{m->dH, 1, kH, nullptr, nullptr};
-    Opnd b{m->fprof, 1, kD, nullptr, cand};
-    if ((s = gemm(kH, kD, (int)P, a, b, tmp + kH * kD, kD, nullptr, false, st, split)))
-      return s;
-  }
-  assemble_w1_kernel<<<(kW1 + 255) / 256, 256, 0, st>>>(tmp, m->grad);
-  train_reduce_kernel<<<(2 * kH + 2 + 255) / 256, 256, 0, st>>>(m->part, m->lossv, nb, m->grad, loss);
-  if ((s = check_hip(hipGetLastError(), "train reduce"))) return s;
-  if (grad_out &&
-      (s = check_hip(hipMemcpyAsync(grad_out, m->grad, 4ull * kParams, hipMemcpyDeviceToDevice, st),
-                     "copy grad")))
+  for (uint32_t f = 0; f < NF && n < kCand; f++)
+    if ((int32_t)f != L && !seen((int32_t)f)) row[n++] = (int32_t)f;
+  // fewer than 64 fragments: the negatives found so far again (the label
+  // itself when it is the only fragment)
+  for (int j = n; j < kCand; j++) row[j] = n > 1 ? row[1 + (j - n) % (n - 1)] : L;
+}
+
+__global__ void fill_words_kernel(uint32_t* __restrict__ p, uint32_t v, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Profile rows of both strands of the batch reads: rows[2b + s] = 2 bidx[b] + s.
+__global__ void batch_rows_kernel(const int32_t* __restrict__ bidx, uint32_t B,
+                                  int32_t* __restrict__ rows) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 2 * B) rows[i] = 2 * bidx[i >> 1] + (int32_t)(i & 1);
+}
+
+// hits += number of reads r (lens > 0) whose label fragment is among its K
+// candidates.
+__global__ void count_hits_kernel(const int32_t* __restrict__ cand, uint32_t K,
+                                  const maxss_top2* __restrict__ labels,
+                                  const uint32_t* __restrict__ lens, uint32_t n,
+                                  uint32_t* __restrict__ hits) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || lens[i] == 0) return;
+  const int32_t L = labels[i].frag[0];
+  if (L < 0) return;
+  for (uint32_t k = 0; k < K; k++)
+    if (cand[(uint64_t)i * K + k] == L) {
+      atomicAdd(hits, 1u);
+      return;
+    }
+}
+
+}  // namespace maxss
+
+static maxss_status model_from_host(const float* params, maxss_model** out) {
+  Model* m = new (std::nothrow) Model();
+  if (!m) return fail(MAXSS_ENOMEM, "host allocation");
+  maxss_status s;
+  do {
+    if ((s = check_hip(hipGetDevice(&m->device), "hipGetDevice"))) break;
+    if ((s = check_hip(hipMalloc((void**)&m->master, 4ull * kParams), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->adam_m, 4ull * kParams), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->adam_v, 4ull * kParams), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->W1a, 2ull * kH * kD), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->W1b, 2ull * kH * kD), "alloc")) ||
+        (s = check_hip(hipMalloc((void**)&m->w2f, 4ull * kH), "alloc")))
+      break;
+    if ((s = check_hip(hipMemcpy(m->master, params, 4ull * kParams, hipMemcpyHostToDevice), "copy")) ||
+        (s = check_hip(hipMemset(m->adam_m, 0, 4ull * kParams), "memset")) ||
+        (s = check_hip(hipMemset(m->adam_v, 0, 4ull * kParams), "memset")))
+      break;
+    if ((s = refresh_shadow(m, nullptr))) break;
+    if ((s = check_hip(hipDeviceSynchronize(), "sync"))) break;
+  } while (0);
+  if (s) {
+    maxss_model_free(reinterpret_cast<maxss_model*>(m));
     return s;
-  if (lr > 0.f) {
-    m->step++;
-    const float b1c = 1.f - powf(0.9f, (float)m->step), b2c = 1.f - powf(0.999f, (float)m->step);
-    adam_kernel<<<(kParams + 255) / 256, 256, 0, st>>>(m->master, m->adam_m, m->adam_v, m->grad,
-                                                       kParams, lr, 0.9f, 0.999f, 1e-8f, b1c, b2c);
-    if ((s = check_hip(hipGetLastError(), "adam_kernel"))) return s;
-    if ((s = refresh_shadow(m, st))) return s;
   }
+  *out = reinterpret_cast<maxss_model*>(m);
   return MAXSS_OK;
+}
+
+extern "C" maxss_status maxss_model_create(uint32_t seed, uint32_t init, maxss_model** out) {
+  clear_error();
+  if (!out) return fail(MAXSS_EINVAL, "NULL argument");
+  if (init != MAXSS_INIT_GLOROT && init != MAXSS_INIT_PROFILE_MATCH)
+    return fail(MAXSS_EINVAL, "unknown initialisation %u", init);
+  std::vector<float> p;
+  init_params(seed, init, p);
+  return model_from_host(p.data(), out);
+}
+
+extern "C" maxss_status maxss_model_from_params(const float* params, maxss_model** out) {
+  clear_error();
+  if (!params || !out) return fail(MAXSS_EINVAL, "NULL argument");
+  return model_from_host(params, out);
+}
+
+extern "C" maxss_status maxss_choose_acceptance(uint32_t n, const float* margin,
+                                                const int32_t* best_score, const uint8_t* correct,
+                                                float target, float* tau, int32_t* min_score,
+                                                float* accept_frac, float* agreement) {
+  clear_error();
+  if (!tau || !min_score || (n && (!margin || !best_score || !correct)))
+    return fail(MAXSS_EINVAL, "NULL argument");
+  if (!(target >= 0.0f && target <= 1.0f)) return fail(MAXSS_EINVAL, "target must lie in [0, 1]");
+  // misses allowed among the n reads (a fallen-back read always agrees); the
+  // slack of 1e-6 n absorbs the float rounding of `target` (0.8f < 0.8)
+  const double budget = (1.0 - (double)target) * (double)n * (1.0 + 1e-6) + 1e-6 * (double)n + 1e-9;
+  std::vector<uint32_t> idx(n);
+  for (uint32_t i = 0; i < n; i++) idx[i] = i;
+  // score rule alone: accept every read whose best exact score reaches the
+  // threshold; the smallest threshold within the budget (ties accept together)
+  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+    return best_score[a] != best_score[b] ? best_score[a] > best_score[b] : a < b;
+  });
+  int32_t ms = -1;
+  double miss = 0;
+  for (uint32_t p = 0; p < n;) {
+    uint32_t q = p;
+    double add = 0;
+    while (q < n && best_score[idx[q]] == best_score[idx[p]]) add += correct[idx[q++]] ? 0 : 1;
+    if (best_score[idx[p]] < 0 || miss + add > budget) break;
+    miss += add;
+    ms = best_score[idx[p]];
+    p = q;
+  }
+  // margin rule on the reads the score rule leaves: the smallest tau within
+  // what is left of the budget
+  std::vector<uint32_t> rest;
+  for (uint32_t i = 0; i < n; i++)
+    if (ms < 0 || best_score[i] < ms) rest.push_back(i);
+  std::sort(rest.begin(), rest.end(), [&](uint32_t a, uint32_t b) {
+    return margin[a] != margin[b] ? margin[a] > margin[b] : a < b;
+  });
+  float t = INFINITY;
+  for (size_t p = 0; p < rest.size();) {
+    size_t q = p;
+    double add = 0;
+    while (q < rest.size() && margin[rest[q]] == margin[rest[p]]) add += correct[rest[q++]] ? 0 : 1;
+    if (!(margin[rest[p]] > -INFINITY) || miss + add > budget) break;
+    miss += add;
+    t = margin[rest[p]];
+    p = q;
+  }
+  uint32_t acc = 0;
+  for (uint32_t i = 0; i < n; i++)
+    if (margin[i] >= t || (ms >= 0 && best_score[i] >= ms)) acc++;
+  *tau = t;
+  *min_score = ms;
+  if (accept_frac) *accept_frac = n ? (float)acc / (float)n : 0.0f;
+  if (agreement) *agreement = n ? (float)(1.0 - miss / (double)n) : 1.0f;
+  return MAXSS_OK;
+}
+
+namespace maxss {
+
+// The read order of epoch e: the valid training reads sorted by (draw r of
+// stream kStreamOrder + e, r).
+static void epoch_order(uint64_t seed, uint64_t e, const std::vector<int32_t>& valid,
+                        std::vector<int32_t>& out) {
+  const uint64_t key = sm_key(seed, kStreamOrder + e);
+  std::vector<std::pair<uint64_t, int32_t>> kv(valid.size());
+  for (size_t j = 0; j < valid.size(); j++) kv[j] = {sm_draw(key, (uint64_t)valid[j]), valid[j]};
+  std::sort(kv.begin(), kv.end());
+  out.resize(valid.size());
+  for (size_t j = 0; j < kv.size(); j++) out[j] = kv[j].second;
+}
+
+// Encoded reads [a, n) of `er` (rows are contiguous per read).
+static EncodedReads encoded_tail(const EncodedReads& er, uint32_t a) {
+  EncodedReads t = er;
+  t.sel4 = er.sel4 + (uint64_t)a * 2 * (er.mstride / 8);
+  t.codes = er.codes + (uint64_t)a * er.mstride;
+  t.lens = er.lens + a;
+  if (er.qsc) t.qsc = er.qsc + (uint64_t)a * er.mstride;
+  return t;
+}
+
+}  // namespace maxss
+
+extern "C" maxss_status maxss_model_train(maxss_model* model, const maxss_index* index,
+                                          const maxss_reads* reads, const maxss_top2* labels,
+                                          const maxss_train_opts* opts, maxss_train_stats* stats,
+                                          void* stream) {
+  clear_error();
+  Model* m = reinterpret_cast<Model*>(model);
+  const Index* ix = reinterpret_cast<const Index*>(index);
+  if (!m || !ix || !reads || !labels || !opts || !stats) return fail(MAXSS_EINVAL, "NULL argument");
+  if (!reads->on_device) return fail(MAXSS_EINVAL, "training takes device reads");
+  if (reads->n == 0 || !reads->seq || !reads->offsets) return fail(MAXSS_EINVAL, "no reads");
+  const maxss_train_opts o = *opts;
+  if (o.batch == 0 || o.batch > 65536) return fail(MAXSS_EINVAL, "batch must be in 1..65536");
+  if (o.K == 0 || o.K > 4096) return fail(MAXSS_EINVAL, "K must be in 1..4096");
+  if (o.hard_negatives > kCand - 2) return fail(MAXSS_EINVAL, "hard_negatives must be <= 62");
+  if (!(o.val_fraction >= 0.0f && o.val_fraction <= 0.9f))
+    return fail(MAXSS_EINVAL, "val_fraction must lie in [0, 0.9]");
+  if (!(o.target_agreement >= 0.0f && o.target_agreement <= 1.0f))
+    return fail(MAXSS_EINVAL, "target_agreement must lie in [0, 1]");
+  if (!(o.lr >= 0.0f)) return fail(MAXSS_EINVAL, "lr must be >= 0");
+  maxss_status s;
+  if ((s = require_quals(ix, reads))) return s;
+  int cur = 0;
+  if ((s = check_hip(hipGetDevice(&cur), "hipGetDevice"))) return s;
+  if (cur != ix->device || cur != m->device)
+    return fail(MAXSS_ESTATE, "index, model and current device differ");
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t n = reads->n, NF = ix->NF, B = o.batch;
+  const uint32_t n_val = (uint32_t)((double)n * (double)o.val_fraction);
+  const uint32_t n_train = n - n_val;
+  const uint32_t Kc = o.K < NF ? o.K : NF;
+  memset(stats, 0, sizeof(*stats));
+  stats->n_train = n_train;
+  stats->n_val = n_val;
+  std::vector<maxss_top2> hl(n);
+  if ((s = check_hip(hipMemcpyAsync(hl.data(), labels, sizeof(maxss_top2) * n, hipMemcpyDeviceToHost, st),
+                     "copy labels")) ||
+      (s = check_hip(hipStreamSynchronize(st), "sync")))
+    return s;
+  auto labelled = [&](uint32_t i) {
+    return hl[i].frag[0] >= 0 && (uint32_t)hl[i].frag[0] < NF &&
+           (hl[i].strand[0] == 0 || hl[i].strand[0] == 1);
+  };
+  std::vector<int32_t> valid;
+  for (uint32_t i = 0; i < n_train; i++)
+    if (labelled(i)) valid.push_back((int32_t)i);
+  uint32_t nv_val = 0;
+  for (uint32_t i = n_train; i < n; i++) nv_val += labelled(i) ? 1u : 0u;
+  if (o.steps > 0 && valid.empty()) return fail(MAXSS_EINVAL, "no labelled training reads");
+  DeviceReads dr;
+  dr.seq = reads->seq;
+  dr.off = reads->offsets;
+  dr.qual = reads->qual;
+  dr.n = n;
+  EncodedReads er;
+  ScanWork wc;
+  uint16_t* rprof = nullptr;
+  int32_t *bidx = nullptr, *cand = nullptr, *rows2 = nullptr, *hardc = nullptr, *cand_v = nullptr;
+  float *trace = nullptr, *best = nullptr, *Ah = nullptr, *Bf = nullptr, *Sh = nullptr;
+  float *mg = nullptr, *mg_v = nullptr;
+  uint32_t *hits = nullptr, *ones = nullptr;
+  uint8_t *fb = nullptr, *fb_v = nullptr;
+  maxss_top2* oc = nullptr;
+  const uint32_t hk = o.hard_negatives ? o.hard_negatives + 1 : 0;
+  std::vector<float> trace_h(o.steps ? o.steps : 1);
+  do {
+    if ((s = ensure_fprof(m, ix, st))) break;
+    if ((s = ensure_train_scratch(m, ix, B))) break;
+    if ((s = alloc_encoded(ix, n, st, &er))) break;
+    if ((s = encode_reads_into(ix, dr, st, er))) break;
+    if ((s = check_hip(hipMallocAsync((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&bidx, 4ull * B, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&cand, 4ull * B * kCand, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&trace, 4ull * (o.steps ? o.steps : 1), st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&best, 4ull * kParams, st), "alloc")) ||
+        (s = check_hip(hipMallocAsync((void**)&hits, 4, st), "alloc")))
+      break;
+    profile_kernel<<<(2 * n + 3) / 4, 256, 0, st>>>(er.codes, er.lens, er.mstride, n, nullptr, 0, 0,
+                                                     rprof, nullptr);
+    if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
+    if (hk) {
+      if ((s = check_hip(hipMallocAsync((void**)&rows2, 8ull * B, st), "alloc")) ||
+          (s = check_hip(hipMallocAsync((void**)&hardc, 4ull * B * hk, st), "alloc")) ||
+          (s = check_hip(hipMallocAsync((void**)&Ah, 4ull * 2 * B * kH, st), "alloc")) ||
+          (s = check_hip(hipMallocAsync((void**)&Bf, 4ull * NF * kH, st), "alloc")) ||
+          (s = check_hip(hipMallocAsync((void**)&Sh, 4ull * B * NF, st), "alloc")) ||
+          (s = check_hip(hipMallocAsync((void**)&mg, 4ull * B, st), "alloc")) ||
+          (s = check_hip(hipMallocAsync((void**)&fb, B, st), "alloc")) ||
+          (s = check_hip(hipMallocAsync((void**)&ones, 4ull * B, st), "alloc")))
+        break;
+      fill_words_kernel<<<(B + 255) / 256, 256, 0, st>>>(ones, 1u, B);
+    }
+    if (n_val &&
+        ((s = check_hip(hipMallocAsync((void**)&cand_v, 4ull * n_val * o.K, st), "alloc")) ||
+         (s = check_hip(hipMallocAsync((void**)&mg_v, 4ull * n_val, st), "alloc")) ||
+         (s = check_hip(hipMallocAsync((void**)&fb_v, n_val, st), "alloc")) ||
+         (s = check_hip(hipMallocAsync((void**)&oc, sizeof(maxss_top2) * n_val, st), "alloc"))))
+      break;
+    const EncodedReads er_val = encoded_tail(er, n_train);
+    // held-out recall@K of the current parameters (-1 without held-out reads)
+    auto evaluate = [&](float* r) -> maxss_status {
+      *r = -1.0f;
+      if (!nv_val) return MAXSS_OK;
+      maxss_status q;
+      if ((q = propose_impl(ix, m, er_val, n_val, o.K, 0.0f, cand_v, mg_v, fb_v, st))) return q;
+      fill_words_kernel<<<1, 64, 0, st>>>(hits, 0u, 1u);
+      count_hits_kernel<<<(n_val + 255) / 256, 256, 0, st>>>(cand_v, o.K, labels + n_train,
+                                                             er_val.lens, n_val, hits);
+      uint32_t h = 0;
+      if ((q = check_hip(hipGetLastError(), "count_hits_kernel")) ||
+          (q = check_hip(hipMemcpyAsync(&h, hits, 4, hipMemcpyDeviceToHost, st), "copy hits")) ||
+          (q = check_hip(hipStreamSynchronize(st), "sync")))
+        return q;
+      *r = (float)h / (float)nv_val;
+      return MAXSS_OK;
+    };
+    float rec = 0;
+    if ((s = evaluate(&rec))) break;
+    stats->val_recall_init = stats->val_recall_best = rec;
+    if ((s = check_hip(hipMemcpyAsync(best, m->master, 4ull * kParams, hipMemcpyDeviceToDevice, st),
+                       "copy params")))
+      break;
+    const uint64_t nkey = sm_key(o.seed, kStreamNeg);
+    const uint64_t nvalid = valid.size();
+    std::vector<int32_t> order, hb(B);
+    uint64_t order_epoch = ~0ull;
+    bool evaluated_last = true;
+    for (uint32_t t = 0; t < o.steps && !s; t++) {
+      for (uint32_t b = 0; b < B; b++) {
+        const uint64_t p = (uint64_t)t * B + b, e = p / nvalid;
+        if (e != order_epoch) {
+          epoch_order(o.seed, e, valid, order);
+          order_epoch = e;
+        }
+        hb[b] = order[p % nvalid];
+      }
+      if ((s = check_hip(hipMemcpyAsync(bidx, hb.data(), 4ull * B, hipMemcpyHostToDevice, st),
+                         "copy batch")))
+        break;
+      if (hk) {
+        // the model's best fragments for the batch reads (both strands)
+        batch_rows_kernel<<<(2 * B + 255) / 256, 256, 0, st>>>(bidx, B, rows2);
+        Opnd a{rprof, kD, 1, rows2, nullptr};
+        Opnd w{m->W1a, kD, 1, nullptr, nullptr};
+        if ((s = gemm((int)(2 * B), kH, kD, a, w, Ah, kH, m->master + kW1, false, st))) break;
+        if ((s = frag_side(m, m->fprof, NF, Bf, st))) break;
+        dim3 grid((NF + 63) / 64, (B + 31) / 32);
+        pair_kernel<<<grid, 256, 0, st>>>(Ah, Bf, m->w2f, host_b2(m), B, NF, Sh, NF);
+        topk_kernel<<<B, 256, 0, st>>>(Sh, NF, NF, hk, 0.0f, ones, 0, hardc, mg, fb);
+        if ((s = check_hip(hipGetLastError(), "hard negatives"))) break;
+      }
+      negatives_kernel<<<(B + 63) / 64, 64, 0, st>>>(bidx, labels, hk ? hardc : nullptr, hk,
+                                                      o.hard_negatives, nkey, t, B, NF, cand, m->rsel);
+      if ((s = check_hip(hipGetLastError(), "negatives_kernel"))) break;
+      if (o.cand_trace &&
+          (s = check_hip(hipMemcpyAsync(o.cand_trace + (uint64_t)t * B * kCand, cand,
+                                        4ull * B * kCand, hipMemcpyDeviceToHost, st),
+                         "copy candidates")))
+        break;
+      if ((s = train_step_impl(m, ix, rprof, m->rsel, cand, B, o.lr, trace + t, nullptr, st))) break;
+      stats->steps_run = t + 1;
+      evaluated_last = false;
+      if (o.eval_every && (t + 1) % o.eval_every == 0) {
+        if ((s = evaluate(&rec))) break;
+        evaluated_last = true;
+        if (rec > stats->val_recall_best) {
+          stats->val_recall_best = rec;
+          stats->best_step = t + 1;
+          if ((s = check_hip(hipMemcpyAsync(best, m->master, 4ull * kParams, hipMemcpyDeviceToDevice,
+                                            st),
+                             "copy params")))
+            break;
+        }
+      }
+    }
+    if (s) break;
+    if (!evaluated_last) {
+      if ((s = evaluate(&rec))) break;
+      if (rec > stats->val_recall_best) {
+        stats->val_recall_best = rec;
+        stats->best_step = stats->steps_run;
+        if ((s = check_hip(hipMemcpyAsync(best, m->master, 4ull * kParams, hipMemcpyDeviceToDevice, st),
+                           "copy params")))
+          break;
+      }
+    }
+    if (stats->best_step != stats->steps_run || !nv_val) {
+      // keep the parameters of the best held-out recall (the initial ones
+      // when no step improved it); without held-out reads, the last ones
+      if (nv_val &&
+          ((s = check_hip(hipMemcpyAsync(m->master, best, 4ull * kParams, hipMemcpyDeviceToDevice, st),
+                          "copy params")) ||
+           (s = refresh_shadow(m, st))))
+        break;
+      if (!nv_val) stats->best_step = stats->steps_run;
+    }
+    if (o.steps) {
+      if ((s = check_hip(hipMemcpyAsync(trace_h.data(), trace, 4ull * o.steps, hipMemcpyDeviceToHost, st),
+                         "copy losses")) ||
+          (s = check_hip(hipStreamSynchronize(st), "sync")))
+        break;
+      stats->loss_first = trace_h[0];
+      stats->loss_last = trace_h[stats->steps_run ? stats->steps_run - 1 : 0];
+      if (o.loss_trace) memcpy(o.loss_trace, trace_h.data(), 4ull * o.steps);
+    }
+    // thresholds on the held-out reads: the network's margins and the exact
+    // best score among the candidates against the full scan's best fragment
+    stats->tau = INFINITY;
+    stats->min_score = -1;
+    if (nv_val) {
+      if ((s = propose_impl(ix, m, er_val, n_val, o.K, 0.0f, cand_v, mg_v, fb_v, st))) break;
+      if ((s = alloc_scan_work(ix, n_val, (uint64_t)n_val * (Kc < 16 ? Kc : 16), true, st, &wc))) break;
+      if ((s = candidate_scan(ix, er_val, er_val.lens, n_val, cand_v, o.K, Kc, oc, wc, st))) break;
+      std::vector<float> hm(n_val);
+      std::vector<maxss_top2> ho(n_val);
+      if ((s = check_hip(hipMemcpyAsync(hm.data(), mg_v, 4ull * n_val, hipMemcpyDeviceToHost, st),
+                         "copy margins")) ||
+          (s = check_hip(hipMemcpyAsync(ho.data(), oc, sizeof(maxss_top2) * n_val, hipMemcpyDeviceToHost,
+                                        st),
+                         "copy records")) ||
+          (s = check_hip(hipStreamSynchronize(st), "sync")))
+        break;
+      std::vector<float> vm;
+      std::vector<int32_t> vs;
+      std::vector<uint8_t> vc;
+      for (uint32_t j = 0; j < n_val; j++) {
+        if (!labelled(n_train + j)) continue;
+        vm.push_back(hm[j]);
+        vs.push_back(ho[j].frag[0] >= 0 ? ho[j].score[0] : -1);
+        vc.push_back(ho[j].frag[0] == hl[n_train + j].frag[0] ? 1 : 0);
+      }
+      if ((s = maxss_choose_acceptance((uint32_t)vm.size(), vm.data(), vs.data(), vc.data(),
+                                       o.target_agreement, &stats->tau, &stats->min_score,
+                                       &stats->val_accept, &stats->val_agreement)))
+        break;
+    }
+  } while (0);
+  void* ps[] = {rprof, bidx, cand, trace, best, hits, rows2, hardc, Ah, Bf, Sh, mg, fb, ones,
+                cand_v, mg_v, fb_v, oc};
+  for (void* p : ps)
+    if (p) (void)hipFreeAsync(p, st);
+  release_scan_work(&wc, true, st);
+  release_encoded(&er, st);
+  const maxss_status s2 = check_hip(hipStreamSynchronize(st), "sync");
+  return s ? s : s2;
 }

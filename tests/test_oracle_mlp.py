@@ -269,3 +269,66 @@ def test_forward_hand_computed_with_biases_and_negative_preactivation():
     # profile unit 0's pre-activation is 1 + 0.5 = 1.5, so y = 3 + 0.5 - 0.75
     loss, yl, _ = mlp.loss_and_grad(p, vr[None, :], np.stack([vf, np.zeros(256)])[None, :, :])
     assert yl[0, 0] == 4.75 and yl[0, 1] == 2.75
+
+
+# ------------------------------------------- training random numbers (oracle)
+
+def test_splitmix64_published_values():
+    # the generator's first outputs from state 0 and from state 1234567
+    # (state += 0x9E3779B97F4A7C15, then the output function)
+    assert [mlp.mix64(0 + (k + 1) * mlp.GAMMA) for k in range(3)] == \
+        [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [mlp.mix64(1234567 + (k + 1) * mlp.GAMMA) for k in range(5)] == \
+        [6457827717110365317, 3203168211198807973, 9817491932198370423,
+         4593380528125082431, 16408922859458223821]
+    key = mlp.sm_key(5, 2)
+    assert mlp.sm_draw(key, 3) == mlp.mix64(key + 4 * mlp.GAMMA)
+
+
+def test_init_params_glorot_statistics():
+    p = mlp.init_params(9, 0)
+    W1, b1, w2, b2 = mlp.unpack(p)
+    a1, a2 = np.sqrt(6.0 / 768), np.sqrt(6.0 / 257)
+    assert np.abs(W1).max() <= a1 and np.abs(w2).max() <= a2
+    assert (b1 == 0).all() and b2 == 0
+    # uniform on [-a, a]: mean 0 and variance a^2 / 3 within 5 standard errors
+    n = W1.size
+    assert abs(W1.mean()) < 5 * a1 / np.sqrt(3 * n)
+    assert abs(W1.var() - a1 ** 2 / 3) < 5 * a1 ** 2 * np.sqrt(4 / 45 / n)
+    assert not (mlp.init_params(10, 0) == p).all()
+    q = mlp.init_params(9, 1)
+    W1, b1, w2, b2 = mlp.unpack(q)
+    assert (np.diag(W1[:, :256]) == 8).all() and (np.diag(W1[:, 256:]) == 1).all()
+    assert np.count_nonzero(W1) == 512 and (b1 == -np.float32(0.2)).all() and (w2 == 1).all()
+
+
+def test_batch_reads_visit_every_read_once_per_epoch():
+    valid = list(range(0, 90, 3))                       # 30 labelled reads
+    seen = [r for t in range(6) for r in mlp.batch_reads(4, t, 5, valid)]
+    assert sorted(seen) == valid                        # 6 steps x 5 = one epoch
+    nxt = [r for t in range(6, 12) for r in mlp.batch_reads(4, t, 5, valid)]
+    assert sorted(nxt) == valid and nxt != seen
+    assert mlp.batch_reads(4, 0, 5, valid) != mlp.batch_reads(5, 0, 5, valid)
+
+
+def test_batch_candidates_rule():
+    NF = 300
+    rows = [mlp.batch_candidates(3, t, 8, b, (7 * t + b) % NF, -1 if b % 2 else (b + 1) % NF, NF)
+            for t in range(40) for b in range(8)]
+    counts = np.zeros(NF)
+    for k, row in enumerate(rows):
+        t, b = divmod(k, 8)
+        lab = (7 * t + b) % NF
+        assert len(row) == 64 and row[0] == lab and lab not in row[1:]
+        assert len(set(row)) == 64 and all(0 <= f < NF for f in row)
+        if b % 2 == 0 and (b + 1) % NF != lab:
+            assert row[1] == (b + 1) % NF
+        counts[row[2:]] += 1
+    # the uniform draws cover the fragments evenly (chi-square, 299 dof)
+    e = counts.sum() / NF
+    assert ((counts - e) ** 2 / e).sum() < 299 + 6 * np.sqrt(2 * 299)
+    # fewer fragments than candidates: every other fragment, then repeats
+    small = mlp.batch_candidates(1, 0, 1, 0, 2, -1, 5)
+    assert small[0] == 2 and sorted(set(small[1:])) == [0, 1, 3, 4]
+    assert all(small[5 + j] == small[1 + j % 4] for j in range(59))
+    assert mlp.batch_candidates(1, 0, 1, 0, 0, -1, 1) == [0] * 64

@@ -1,41 +1,64 @@
-"""Host-side logic of the proposal training and evaluation loop (no GPU): threshold choice,
-recall and agreement."""
+"""Host-side choice of the proposal's acceptance thresholds
+(maxss_choose_acceptance, no GPU): against a brute force over every
+threshold pair on random held-out sets, and on hand-made cases."""
 import numpy as np
+import pytest
 
 import paper_1403_2136_amd as mx
-from paper_1403_2136_amd import proposal as P
 
 
-def _labels(frags):
-    a = np.zeros(len(frags), dtype=mx.TOP2_DTYPE)
-    a["frag"][:, 0] = frags
-    return a
+def _agreement(margin, score, correct, tau, ms):
+    acc = (margin >= tau) | ((ms >= 0) & (score >= ms))
+    return 1.0 - (acc & (correct == 0)).sum() / margin.size, acc.mean()
 
 
-def test_recall():
-    cand = np.array([[1, 2, 3], [4, 5, 6], [7, 8, 9]])
-    assert P.recall(cand, _labels([2, 9, 9])).tolist() == [True, False, True]
+def _brute(margin, score, correct, target):
+    """The smallest min_score (or none) keeping the agreement >= target with
+    the score rule alone, then the smallest margin of a read that rule
+    leaves (or +inf) that keeps it."""
+    n = margin.size
+    ok = lambda a: a >= target - 1e-9
+    ms = -1
+    for s in sorted(set(score[score >= 0].tolist())):
+        if ok(_agreement(margin, score, correct, np.inf, s)[0]):
+            ms = s
+            break
+    tau = np.inf
+    left = margin[(ms < 0) | (score < ms)]
+    for t in sorted(set(left.tolist())):
+        if ok(_agreement(margin, score, correct, t, ms)[0]):
+            tau = t
+            break
+    return tau, ms
 
 
-def test_choose_margin_falls_back_the_smallest_margins():
-    # reads 0..9 with margins 0.1..1.0; the misses are the reads with margins 0.1 and 0.3
-    margins = np.arange(1, 11) / 10.0
-    cand = np.zeros((10, 2), dtype=np.int64)
-    labels = _labels(np.zeros(10, dtype=np.int64))
-    cand[[0, 2], :] = 5                                  # label 0 missing for reads 0 and 2
-    m32 = margins.astype(np.float32)
-    tau = P.choose_margin(cand, m32, labels, 1.0)
-    assert (m32 < tau).sum() == 3                      # reads with margins 0.1, 0.2, 0.3
-    assert (m32 < P.choose_margin(cand, m32, labels, 0.8)).sum() == 0   # 8/10 already agree
-    assert (m32 < P.choose_margin(np.zeros((10, 2), np.int64), m32, labels, 1.0)).sum() == 0
+@pytest.mark.parametrize("seed", range(12))
+def test_acceptance_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 60))
+    score = rng.integers(-1, 12, n).astype(np.int32)
+    margin = np.round(rng.uniform(0, 1, n), 1).astype(np.float32)   # ties
+    correct = (rng.uniform(size=n) < 0.7).astype(np.uint8)
+    correct[score >= 9] = 1
+    target = float(rng.choice([0.5, 0.8, 0.9, 0.95, 1.0]))
+    tau, ms, acc, agr = mx.maxss_choose_acceptance(margin, score, correct, target)
+    bt, bms = _brute(margin.astype(np.float64), score, correct, target)
+    assert ms == bms
+    assert tau == bt or (np.isinf(tau) and np.isinf(bt))
+    a, f = _agreement(margin, score, correct, tau, ms)
+    assert a >= target - 1e-6 and abs(a - agr) < 1e-6 and abs(f - acc) < 1e-6
 
 
-def test_agreements():
-    a = np.zeros(3, dtype=mx.TOP2_DTYPE)
-    b = np.zeros(3, dtype=mx.TOP2_DTYPE)
-    a["frag"][:, 0] = [1, 2, 3]
-    b["frag"][:, 0] = [1, 2, 4]
-    a["score"][:, 0] = [5, 5, 5]
-    b["score"][:, 0] = [5, 5, 5]
-    assert abs(P.top1_agreement(a, b) - 2 / 3) < 1e-12
-    assert P.score_agreement(a, b) == 1.0
+def test_acceptance_hand_cases():
+    # every best candidate right: everything is accepted by the lowest score
+    tau, ms, acc, agr = mx.maxss_choose_acceptance([0.1, 0.2], [3, 5], [1, 1], 1.0)
+    assert ms == 3 and acc == 1.0 and agr == 1.0
+    # the best-scoring read is wrong: no score threshold keeps 100%; the
+    # margin rule then accepts the right reads above the wrong one's margin
+    tau, ms, acc, agr = mx.maxss_choose_acceptance([0.5, 0.9, 0.1], [9, 5, 4], [0, 1, 1], 1.0)
+    assert ms == -1 and tau == np.float32(0.9) and abs(acc - 1 / 3) < 1e-6 and agr == 1.0
+    # an empty held-out set accepts nothing
+    tau, ms, acc, agr = mx.maxss_choose_acceptance([], [], [], 0.99)
+    assert ms == -1 and np.isinf(tau) and acc == 0.0 and agr == 1.0
+    with pytest.raises(mx.MaxssError):
+        mx.maxss_choose_acceptance([0.1], [1], [1], 1.5)
