@@ -552,6 +552,14 @@ maxss_status maxss_profile_read(const char* name, double* total_ms, uint32_t* la
  * allocates a small buffer.  Errors: EINVAL (NULL), EDEVICE. */
 maxss_status maxss_roof_int16(double* ops_per_s, void* stream);
 
+/* Test hook for the out-of-memory paths: the n-th device allocation the
+ * library makes from now on (any thread, any call) fails with MAXSS_ENOMEM
+ * without allocating, as an exhausted device would; later allocations
+ * succeed again.  n = 0 turns the hook off.  Every call releases what it
+ * allocated before the failure and leaves its inputs untouched.  Host only;
+ * always MAXSS_OK. */
+maxss_status maxss_fail_alloc_after(uint32_t n);
+
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char* maxss_last_error(void);
 

@@ -96,7 +96,8 @@ EXPORTS = ("maxss_index_genome", "maxss_index_free", "maxss_index_info", "maxss_
            "maxss_proposal_candidates", "maxss_scan_reads_proposed", "maxss_model_train_step",
            "maxss_model_train", "maxss_choose_acceptance",
            "maxss_mapq", "maxss_sam_header", "maxss_sam_records",
-           "maxss_profile_enable", "maxss_profile_read", "maxss_roof_int16", "maxss_last_error",
+           "maxss_profile_enable", "maxss_profile_read", "maxss_roof_int16",
+           "maxss_fail_alloc_after", "maxss_last_error",
            "maxss_version")
 MLP_PARAMS = 131585
 MAXSS_INIT_GLOROT, MAXSS_INIT_PROFILE_MATCH = 0, 1
@@ -191,6 +192,8 @@ def lib():
         L.maxss_profile_enable.argtypes = [c.c_int]
         L.maxss_profile_read.restype = c.c_int
         L.maxss_profile_read.argtypes = [c.c_char_p, c.POINTER(c.c_double), c.POINTER(c.c_uint32)]
+        L.maxss_fail_alloc_after.restype = c.c_int
+        L.maxss_fail_alloc_after.argtypes = [c.c_uint32]
         L.maxss_roof_int16.restype = c.c_int
         L.maxss_roof_int16.argtypes = [c.POINTER(c.c_double), c.c_void_p]
         L.maxss_last_error.restype = c.c_char_p
@@ -282,6 +285,11 @@ def maxss_profile_read(name: str):
     t, k = ctypes.c_double(), ctypes.c_uint32()
     _check(lib().maxss_profile_read(name.encode(), ctypes.byref(t), ctypes.byref(k)))
     return t.value, k.value
+
+
+def maxss_fail_alloc_after(n: int) -> None:
+    """Test hook: the n-th device allocation from now fails (0: off)."""
+    _check(lib().maxss_fail_alloc_after(n))
 
 
 def maxss_roof_int16(stream=None) -> float:

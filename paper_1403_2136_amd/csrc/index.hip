@@ -41,6 +41,28 @@ maxss_status check_hip(hipError_t e, const char* what) {
   return fail(MAXSS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Countdown of maxss_fail_alloc_after: the allocation that brings it from 1
+// to 0 fails; 0 = off.
+static std::atomic<uint32_t> g_fail_alloc{0};
+
+static bool alloc_should_fail() {
+  uint32_t v = g_fail_alloc.load();
+  while (v != 0) {
+    if (g_fail_alloc.compare_exchange_weak(v, v - 1)) return v == 1;
+  }
+  return false;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (alloc_should_fail()) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t dev_malloc_async(void** p, size_t bytes, hipStream_t st) {
+  if (alloc_should_fail()) return hipErrorOutOfMemory;
+  return hipMallocAsync(p, bytes, st);
+}
+
 uint8_t host_code(char c) {
   switch (c) {
     case 'A': case 'a': return kA;
@@ -91,10 +113,10 @@ maxss_status stage_reads(const maxss_reads* r, hipStream_t st, DeviceReads* d) {
   uint64_t a = r->offsets[0], b = r->offsets[r->n];
   uint64_t bytes = b - a;
   maxss_status s;
-  if ((s = check_hip(hipMallocAsync((void**)&d->own_seq, bytes ? bytes : 1, st),
+  if ((s = check_hip(dev_malloc_async((void**)&d->own_seq, bytes ? bytes : 1, st),
                      "hipMallocAsync(reads)")))
     return s;
-  if ((s = check_hip(hipMallocAsync((void**)&d->own_off, sizeof(uint64_t) * (r->n + 1), st),
+  if ((s = check_hip(dev_malloc_async((void**)&d->own_off, sizeof(uint64_t) * (r->n + 1), st),
                      "hipMallocAsync(offsets)")))
     return s;
   std::vector<uint64_t> off(r->n + 1);
@@ -107,7 +129,7 @@ maxss_status stage_reads(const maxss_reads* r, hipStream_t st, DeviceReads* d) {
                      "copy offsets")))
     return s;
   if (r->qual) {
-    if ((s = check_hip(hipMallocAsync((void**)&d->own_qual, bytes ? bytes : 1, st),
+    if ((s = check_hip(dev_malloc_async((void**)&d->own_qual, bytes ? bytes : 1, st),
                        "hipMallocAsync(qualities)")) ||
         (s = check_hip(hipMemcpyAsync(d->own_qual, r->qual + a, bytes, hipMemcpyHostToDevice, st),
                        "copy qualities")))
@@ -249,19 +271,19 @@ maxss_status alloc_encoded(const Index* ix, uint32_t n, hipStream_t st, EncodedR
   e->mstride = read_stride(ix);
   maxss_status s;
   if (qual_mode(ix) &&
-      (s = check_hip(hipMallocAsync((void**)&e->qsc, sizeof(uint16_t) * ((uint64_t)n * e->mstride +
+      (s = check_hip(dev_malloc_async((void**)&e->qsc, sizeof(uint16_t) * ((uint64_t)n * e->mstride +
                                                                          kSlack), st),
                      "hipMallocAsync(position scores)")))
     return s;
-  if ((s = check_hip(hipMallocAsync((void**)&e->sel4,
+  if ((s = check_hip(dev_malloc_async((void**)&e->sel4,
                                     sizeof(uint32_t) * ((uint64_t)n * 2 * (e->mstride / 8) + kSlack),
                                     st),
                      "hipMallocAsync(read codes)")))
     return s;
-  if ((s = check_hip(hipMallocAsync((void**)&e->codes, (uint64_t)n * e->mstride + kSlack, st),
+  if ((s = check_hip(dev_malloc_async((void**)&e->codes, (uint64_t)n * e->mstride + kSlack, st),
                      "hipMallocAsync(read bases)")))
     return s;
-  return check_hip(hipMallocAsync((void**)&e->lens, sizeof(uint32_t) * ((uint64_t)n + 1), st),
+  return check_hip(dev_malloc_async((void**)&e->lens, sizeof(uint32_t) * ((uint64_t)n + 1), st),
                    "hipMallocAsync(lens)");
 }
 
@@ -379,9 +401,9 @@ extern "C" maxss_status maxss_index_genome(const char* seq, uint64_t len,
     else
       g2[i >> 4] |= (uint32_t)c << (2 * (i & 15));
   }
-  if ((s = check_hip(hipMalloc((void**)&ix->g2, g2.size() * 4), "hipMalloc(genome)")) ||
-      (s = check_hip(hipMalloc((void**)&ix->nmask, nm.size() * 4), "hipMalloc(N mask)")) ||
-      (s = check_hip(hipMalloc((void**)&ix->codes, codes.size()), "hipMalloc(codes)")) ||
+  if ((s = check_hip(dev_malloc((void**)&ix->g2, g2.size() * 4), "hipMalloc(genome)")) ||
+      (s = check_hip(dev_malloc((void**)&ix->nmask, nm.size() * 4), "hipMalloc(N mask)")) ||
+      (s = check_hip(dev_malloc((void**)&ix->codes, codes.size()), "hipMalloc(codes)")) ||
       (s = check_hip(hipMemcpy(ix->g2, g2.data(), g2.size() * 4, hipMemcpyHostToDevice),
                      "copy genome")) ||
       (s = check_hip(hipMemcpy(ix->nmask, nm.data(), nm.size() * 4, hipMemcpyHostToDevice),
@@ -455,3 +477,9 @@ extern "C" maxss_status maxss_profile_read(const char* name, double* total_ms,
 extern "C" const char* maxss_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char* maxss_version(void) { return "maxss-gfx950 0.1"; }
+
+extern "C" maxss_status maxss_fail_alloc_after(uint32_t n) {
+  clear_error();
+  g_fail_alloc.store(n);
+  return MAXSS_OK;
+}

@@ -59,6 +59,13 @@ void clear_error();
 // Returns MAXSS_EDEVICE (and records the message) when e != hipSuccess.
 maxss_status check_hip(hipError_t e, const char* what);
 
+// Every device allocation of the library goes through these: hipMalloc and
+// hipMallocAsync, except that the allocation maxss_fail_alloc_after armed
+// returns hipErrorOutOfMemory without allocating (a test hook for the
+// out-of-memory paths).
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t dev_malloc_async(void** p, size_t bytes, hipStream_t st);
+
 // Host-side ASCII -> code, 0xFF for a character outside ACGTN/acgtn.
 uint8_t host_code(char c);
 

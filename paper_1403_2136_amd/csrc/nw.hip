@@ -998,7 +998,7 @@ extern "C" maxss_status maxss_align_top(const maxss_index* index, const maxss_re
     if ((s = stage_reads(reads, st, &dr))) break;
     if ((s = alloc_encoded(ix, n, st, &er))) break;
     if ((s = encode_reads_into(ix, dr, st, er))) break;
-    if ((s = check_hip(hipMallocAsync((void**)&slab, (size_t)sh.grid * ix->p.max_read_len * sh.rowbytes,
+    if ((s = check_hip(dev_malloc_async((void**)&slab, (size_t)sh.grid * ix->p.max_read_len * sh.rowbytes,
                                       st),
                        "alloc NW slab")))
       break;
@@ -1007,9 +1007,9 @@ extern "C" maxss_status maxss_align_top(const maxss_index* index, const maxss_re
       dout = out;
       dcig = cigar;
     } else {
-      if ((s = check_hip(hipMallocAsync((void**)&dtop, sizeof(maxss_top2) * n, st), "alloc top")) ||
-          (s = check_hip(hipMallocAsync((void**)&dout, sizeof(maxss_aln) * n, st), "alloc aln")) ||
-          (s = check_hip(hipMallocAsync((void**)&dcig, (size_t)n * cigar_stride, st), "alloc cigar")) ||
+      if ((s = check_hip(dev_malloc_async((void**)&dtop, sizeof(maxss_top2) * n, st), "alloc top")) ||
+          (s = check_hip(dev_malloc_async((void**)&dout, sizeof(maxss_aln) * n, st), "alloc aln")) ||
+          (s = check_hip(dev_malloc_async((void**)&dcig, (size_t)n * cigar_stride, st), "alloc cigar")) ||
           (s = check_hip(hipMemcpyAsync(dtop, top, sizeof(maxss_top2) * n, hipMemcpyHostToDevice, st),
                          "copy top")))
         break;

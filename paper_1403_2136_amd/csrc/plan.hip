@@ -128,7 +128,7 @@ extern "C" maxss_status maxss_plan_create(const maxss_index* index, uint32_t cap
   do {
     if ((s = alloc_scan_work(ix, capacity, cap, false, nullptr, &p->w))) break;
     if ((s = nw_shape(ix, capacity, pad, &p->nsh))) break;
-    if ((s = check_hip(hipMalloc((void**)&p->slab,
+    if ((s = check_hip(dev_malloc((void**)&p->slab,
                                  (size_t)p->nsh.grid * ix->p.max_read_len * p->nsh.rowbytes),
                        "alloc NW slab")))
       break;
@@ -293,8 +293,8 @@ extern "C" maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sa
       cap = e > cap ? e : cap;
     }
     if ((s = alloc_scan_work(ix, n, cap, false, st, &w))) break;
-    if ((s = check_hip(hipMalloc((void**)&ref, sizeof(maxss_top2) * n), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&got, sizeof(maxss_top2) * n), "alloc")))
+    if ((s = check_hip(dev_malloc((void**)&ref, sizeof(maxss_top2) * n), "alloc")) ||
+        (s = check_hip(dev_malloc((void**)&got, sizeof(maxss_top2) * n), "alloc")))
       break;
     auto timed = [&](const TileOverride* f, maxss_top2* out, float* ms) -> maxss_status {
       maxss_status q;

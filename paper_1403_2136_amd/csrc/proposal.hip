@@ -549,7 +549,7 @@ static maxss_status ensure_fprof(Model* m, const Index* ix, hipStream_t st) {
   m->fprof = nullptr;
   m->fp_ix = nullptr;
   maxss_status s;
-  if ((s = check_hip(hipMalloc((void**)&m->fprof, sizeof(uint16_t) * (size_t)ix->NF * kD),
+  if ((s = check_hip(dev_malloc((void**)&m->fprof, sizeof(uint16_t) * (size_t)ix->NF * kD),
                      "alloc fragment profiles")))
     return s;
   profile_kernel<<<(ix->NF + 3) / 4, 256, 0, st>>>(nullptr, nullptr, 0, 0, ix->codes, ix->F, ix->NF,
@@ -703,22 +703,22 @@ static maxss_status ensure_train_scratch(Model* m, const Index* ix, uint32_t nb)
   maxss_status s;
   m->er.mstride = read_stride(ix);
   const uint64_t P = (uint64_t)cap * kCand;
-  if ((s = check_hip(hipMalloc((void**)&m->er.sel4, 4ull * (cap * 2ull * (m->er.mstride / 8) + 64)),
+  if ((s = check_hip(dev_malloc((void**)&m->er.sel4, 4ull * (cap * 2ull * (m->er.mstride / 8) + 64)),
                      "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->er.codes, (uint64_t)cap * m->er.mstride + 64), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->er.lens, 4ull * (cap + 1)), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->rprof, 2ull * cap * 2 * kD), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->Ar, 4ull * cap * kH), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->Bc, 4ull * P * kH), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->dy, 4ull * P), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->lossv, 4ull * cap), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->dH, 2ull * P * kH), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->dA, 2ull * cap * kH), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->part, 4ull * cap * (2 * kH + 1)), "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->grad,
+      (s = check_hip(dev_malloc((void**)&m->er.codes, (uint64_t)cap * m->er.mstride + 64), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->er.lens, 4ull * (cap + 1)), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->rprof, 2ull * cap * 2 * kD), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->Ar, 4ull * cap * kH), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->Bc, 4ull * P * kH), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->dy, 4ull * P), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->lossv, 4ull * cap), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->dH, 2ull * P * kH), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->dA, 2ull * cap * kH), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->part, 4ull * cap * (2 * kH + 1)), "alloc")) ||
+      (s = check_hip(dev_malloc((void**)&m->grad,
                                 4ull * (kParams + 2 * kH * kD + (size_t)kSplitMax * kH * kD)),
                       "alloc")) ||
-      (s = check_hip(hipMalloc((void**)&m->rsel, 4ull * cap), "alloc"))) {
+      (s = check_hip(dev_malloc((void**)&m->rsel, 4ull * cap), "alloc"))) {
     free_train_scratch(m);
     return s;
   }
@@ -817,7 +817,7 @@ extern "C" maxss_status maxss_profiles(const maxss_index* index, const maxss_rea
         if ((s = stage_reads(reads, st, &dr))) break;
         if ((s = alloc_encoded(ix, n, st, &er))) break;
         if ((s = encode_reads_into(ix, dr, st, er))) break;
-        if ((s = check_hip(hipMallocAsync((void**)&tmp, 2ull * n * 2 * kD, st), "alloc"))) break;
+        if ((s = check_hip(dev_malloc_async((void**)&tmp, 2ull * n * 2 * kD, st), "alloc"))) break;
         profile_kernel<<<(2 * n + 3) / 4, 256, 0, st>>>(er.codes, er.lens, er.mstride, n, nullptr,
                                                          0, 0, tmp, read_prof);
         if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
@@ -826,7 +826,7 @@ extern "C" maxss_status maxss_profiles(const maxss_index* index, const maxss_rea
       }
     }
     if (frag_prof) {
-      if ((s = check_hip(hipMallocAsync((void**)&tmp, 2ull * ix->NF * kD, st), "alloc"))) break;
+      if ((s = check_hip(dev_malloc_async((void**)&tmp, 2ull * ix->NF * kD, st), "alloc"))) break;
       profile_kernel<<<(ix->NF + 3) / 4, 256, 0, st>>>(nullptr, nullptr, 0, 0, ix->codes, ix->F,
                                                         ix->NF, tmp, frag_prof);
       if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
@@ -880,9 +880,9 @@ extern "C" maxss_status maxss_proposal_scores(const maxss_index* index, maxss_mo
     if ((s = stage_reads(reads, st, &dr))) break;
     if ((s = alloc_encoded(ix, n, st, &er))) break;
     if ((s = encode_reads_into(ix, dr, st, er))) break;
-    if ((s = check_hip(hipMallocAsync((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&A, 4ull * n * 2 * kH, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&B, 4ull * ix->NF * kH, st), "alloc")))
+    if ((s = check_hip(dev_malloc_async((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&A, 4ull * n * 2 * kH, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&B, 4ull * ix->NF * kH, st), "alloc")))
       break;
     profile_kernel<<<(2 * n + 3) / 4, 256, 0, st>>>(er.codes, er.lens, er.mstride, n, nullptr, 0, 0,
                                                      rprof, nullptr);
@@ -918,9 +918,9 @@ static maxss_status propose_impl(const Index* ix, Model* m, const EncodedReads& 
   float *A = nullptr, *B = nullptr, *S = nullptr;
   do {
     if ((s = ensure_fprof(m, ix, st))) break;
-    if ((s = check_hip(hipMallocAsync((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&A, 4ull * n * 2 * kH, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&B, 4ull * ix->NF * kH, st), "alloc")))
+    if ((s = check_hip(dev_malloc_async((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&A, 4ull * n * 2 * kH, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&B, 4ull * ix->NF * kH, st), "alloc")))
       break;
     {
       ProfScope prof("profile", st);
@@ -934,7 +934,7 @@ static maxss_status propose_impl(const Index* ix, Model* m, const EncodedReads& 
     uint64_t batch = kScoreBudget / (4ull * ix->NF);
     if (batch < 1) batch = 1;
     if (batch > n) batch = n;
-    if ((s = check_hip(hipMallocAsync((void**)&S, 4ull * batch * ix->NF, st), "alloc scores"))) break;
+    if ((s = check_hip(dev_malloc_async((void**)&S, 4ull * batch * ix->NF, st), "alloc scores"))) break;
     for (uint32_t r0 = 0; r0 < n && !s; r0 += (uint32_t)batch) {
       const uint32_t nb = (uint32_t)((n - r0) < batch ? (n - r0) : batch);
       dim3 grid((ix->NF + 63) / 64, (nb + 31) / 32);
@@ -1018,13 +1018,13 @@ extern "C" maxss_status maxss_scan_reads_proposed(const maxss_index* index, maxs
   do {
     if ((s = alloc_scan_work(ix, n, scan_partial_entries(ix, n, nullptr), true, st, &wf))) break;
     if ((s = encode_reads_into(ix, dr, st, wf.er))) break;
-    if ((s = check_hip(hipMallocAsync((void**)&cand, 4ull * n * K, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&mg, 4ull * n, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&fb, n, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&lens_c, 4ull * n, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&lens_f, 4ull * n, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&oc, sizeof(maxss_top2) * n, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&of, sizeof(maxss_top2) * n, st), "alloc")))
+    if ((s = check_hip(dev_malloc_async((void**)&cand, 4ull * n * K, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&mg, 4ull * n, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&fb, n, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&lens_c, 4ull * n, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&lens_f, 4ull * n, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&oc, sizeof(maxss_top2) * n, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&of, sizeof(maxss_top2) * n, st), "alloc")))
       break;
     if ((s = propose_impl(ix, m, wf.er, n, K, margin_tau, cand, mg, fb, st))) break;
     if ((s = alloc_scan_work(ix, n, (uint64_t)n * (Kc < 16 ? Kc : 16), true, st, &wc))) break;
@@ -1277,12 +1277,12 @@ static maxss_status model_from_host(const float* params, maxss_model** out) {
   maxss_status s;
   do {
     if ((s = check_hip(hipGetDevice(&m->device), "hipGetDevice"))) break;
-    if ((s = check_hip(hipMalloc((void**)&m->master, 4ull * kParams), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->adam_m, 4ull * kParams), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->adam_v, 4ull * kParams), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->W1a, 2ull * kH * kD), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->W1b, 2ull * kH * kD), "alloc")) ||
-        (s = check_hip(hipMalloc((void**)&m->w2f, 4ull * kH), "alloc")))
+    if ((s = check_hip(dev_malloc((void**)&m->master, 4ull * kParams), "alloc")) ||
+        (s = check_hip(dev_malloc((void**)&m->adam_m, 4ull * kParams), "alloc")) ||
+        (s = check_hip(dev_malloc((void**)&m->adam_v, 4ull * kParams), "alloc")) ||
+        (s = check_hip(dev_malloc((void**)&m->W1a, 2ull * kH * kD), "alloc")) ||
+        (s = check_hip(dev_malloc((void**)&m->W1b, 2ull * kH * kD), "alloc")) ||
+        (s = check_hip(dev_malloc((void**)&m->w2f, 4ull * kH), "alloc")))
       break;
     if ((s = check_hip(hipMemcpy(m->master, params, 4ull * kParams, hipMemcpyHostToDevice), "copy")) ||
         (s = check_hip(hipMemset(m->adam_m, 0, 4ull * kParams), "memset")) ||
@@ -1467,33 +1467,33 @@ extern "C" maxss_status maxss_model_train(maxss_model* model, const maxss_index*
     if ((s = ensure_train_scratch(m, ix, B))) break;
     if ((s = alloc_encoded(ix, n, st, &er))) break;
     if ((s = encode_reads_into(ix, dr, st, er))) break;
-    if ((s = check_hip(hipMallocAsync((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&bidx, 4ull * B, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&cand, 4ull * B * kCand, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&trace, 4ull * (o.steps ? o.steps : 1), st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&best, 4ull * kParams, st), "alloc")) ||
-        (s = check_hip(hipMallocAsync((void**)&hits, 4, st), "alloc")))
+    if ((s = check_hip(dev_malloc_async((void**)&rprof, 2ull * n * 2 * kD, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&bidx, 4ull * B, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&cand, 4ull * B * kCand, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&trace, 4ull * (o.steps ? o.steps : 1), st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&best, 4ull * kParams, st), "alloc")) ||
+        (s = check_hip(dev_malloc_async((void**)&hits, 4, st), "alloc")))
       break;
     profile_kernel<<<(2 * n + 3) / 4, 256, 0, st>>>(er.codes, er.lens, er.mstride, n, nullptr, 0, 0,
                                                      rprof, nullptr);
     if ((s = check_hip(hipGetLastError(), "profile_kernel"))) break;
     if (hk) {
-      if ((s = check_hip(hipMallocAsync((void**)&rows2, 8ull * B, st), "alloc")) ||
-          (s = check_hip(hipMallocAsync((void**)&hardc, 4ull * B * hk, st), "alloc")) ||
-          (s = check_hip(hipMallocAsync((void**)&Ah, 4ull * 2 * B * kH, st), "alloc")) ||
-          (s = check_hip(hipMallocAsync((void**)&Bf, 4ull * NF * kH, st), "alloc")) ||
-          (s = check_hip(hipMallocAsync((void**)&Sh, 4ull * B * NF, st), "alloc")) ||
-          (s = check_hip(hipMallocAsync((void**)&mg, 4ull * B, st), "alloc")) ||
-          (s = check_hip(hipMallocAsync((void**)&fb, B, st), "alloc")) ||
-          (s = check_hip(hipMallocAsync((void**)&ones, 4ull * B, st), "alloc")))
+      if ((s = check_hip(dev_malloc_async((void**)&rows2, 8ull * B, st), "alloc")) ||
+          (s = check_hip(dev_malloc_async((void**)&hardc, 4ull * B * hk, st), "alloc")) ||
+          (s = check_hip(dev_malloc_async((void**)&Ah, 4ull * 2 * B * kH, st), "alloc")) ||
+          (s = check_hip(dev_malloc_async((void**)&Bf, 4ull * NF * kH, st), "alloc")) ||
+          (s = check_hip(dev_malloc_async((void**)&Sh, 4ull * B * NF, st), "alloc")) ||
+          (s = check_hip(dev_malloc_async((void**)&mg, 4ull * B, st), "alloc")) ||
+          (s = check_hip(dev_malloc_async((void**)&fb, B, st), "alloc")) ||
+          (s = check_hip(dev_malloc_async((void**)&ones, 4ull * B, st), "alloc")))
         break;
       fill_words_kernel<<<(B + 255) / 256, 256, 0, st>>>(ones, 1u, B);
     }
     if (n_val &&
-        ((s = check_hip(hipMallocAsync((void**)&cand_v, 4ull * n_val * o.K, st), "alloc")) ||
-         (s = check_hip(hipMallocAsync((void**)&mg_v, 4ull * n_val, st), "alloc")) ||
-         (s = check_hip(hipMallocAsync((void**)&fb_v, n_val, st), "alloc")) ||
-         (s = check_hip(hipMallocAsync((void**)&oc, sizeof(maxss_top2) * n_val, st), "alloc"))))
+        ((s = check_hip(dev_malloc_async((void**)&cand_v, 4ull * n_val * o.K, st), "alloc")) ||
+         (s = check_hip(dev_malloc_async((void**)&mg_v, 4ull * n_val, st), "alloc")) ||
+         (s = check_hip(dev_malloc_async((void**)&fb_v, n_val, st), "alloc")) ||
+         (s = check_hip(dev_malloc_async((void**)&oc, sizeof(maxss_top2) * n_val, st), "alloc"))))
       break;
     const EncodedReads er_val = encoded_tail(er, n_train);
     // held-out recall@K of the current parameters (-1 without held-out reads)

@@ -54,7 +54,7 @@ extern "C" maxss_status maxss_roof_int16(double* ops_per_s, void* stream) {
   uint32_t* sink = nullptr;
   double best = 0.0;
   do {
-    if ((s = check_hip(hipMalloc((void**)&sink, sizeof(uint32_t) * grid), "hipMalloc")) ||
+    if ((s = check_hip(dev_malloc((void**)&sink, sizeof(uint32_t) * grid), "hipMalloc")) ||
         (s = check_hip(hipEventCreate(&e0), "hipEventCreate")) ||
         (s = check_hip(hipEventCreate(&e1), "hipEventCreate")))
       break;

@@ -1278,41 +1278,41 @@ maxss_status alloc_scan_work(const Index* ix, uint32_t n, uint64_t partial_cap, 
   w->partial_cap = partial_cap;
   if (stream_ordered) {
     if ((s = alloc_encoded(ix, n, st, &w->er))) return s;
-    if ((s = check_hip(hipMallocAsync((void**)&w->order, sizeof(uint32_t) * n, st), "alloc order")) ||
-        (s = check_hip(hipMallocAsync((void**)&w->hist, sizeof(uint32_t) * nb, st), "alloc hist")) ||
-        (s = check_hip(hipMallocAsync((void**)&w->ctr, sizeof(uint32_t), st), "alloc counter")) ||
-        (s = check_hip(hipMallocAsync((void**)&w->partial, sizeof(int4) * partial_cap, st),
+    if ((s = check_hip(dev_malloc_async((void**)&w->order, sizeof(uint32_t) * n, st), "alloc order")) ||
+        (s = check_hip(dev_malloc_async((void**)&w->hist, sizeof(uint32_t) * nb, st), "alloc hist")) ||
+        (s = check_hip(dev_malloc_async((void**)&w->ctr, sizeof(uint32_t), st), "alloc counter")) ||
+        (s = check_hip(dev_malloc_async((void**)&w->partial, sizeof(int4) * partial_cap, st),
                        "alloc partial")))
       return s;
     if ((ix->p.flags & MAXSS_EXCLUDE_ADJACENT) &&
-        ((s = check_hip(hipMallocAsync((void**)&w->excl, sizeof(int32_t) * n, st), "alloc excl")) ||
-         (s = check_hip(hipMallocAsync((void**)&w->lens2, sizeof(uint32_t) * n, st),
+        ((s = check_hip(dev_malloc_async((void**)&w->excl, sizeof(int32_t) * n, st), "alloc excl")) ||
+         (s = check_hip(dev_malloc_async((void**)&w->lens2, sizeof(uint32_t) * n, st),
                         "alloc lens2")) ||
-         (s = check_hip(hipMallocAsync((void**)&w->again, sizeof(maxss_top2) * n, st),
+         (s = check_hip(dev_malloc_async((void**)&w->again, sizeof(maxss_top2) * n, st),
                         "alloc again"))))
       return s;
     return MAXSS_OK;
   }
   w->er.mstride = read_stride(ix);
   const uint64_t nw = (uint64_t)n * 2 * (w->er.mstride / 8) + 64;
-  if ((s = check_hip(hipMalloc((void**)&w->er.sel4, sizeof(uint32_t) * nw), "alloc read codes")) ||
-      (s = check_hip(hipMalloc((void**)&w->er.codes, (uint64_t)n * w->er.mstride + 64),
+  if ((s = check_hip(dev_malloc((void**)&w->er.sel4, sizeof(uint32_t) * nw), "alloc read codes")) ||
+      (s = check_hip(dev_malloc((void**)&w->er.codes, (uint64_t)n * w->er.mstride + 64),
                      "alloc read bases")) ||
-      (s = check_hip(hipMalloc((void**)&w->er.lens, sizeof(uint32_t) * ((uint64_t)n + 1)),
+      (s = check_hip(dev_malloc((void**)&w->er.lens, sizeof(uint32_t) * ((uint64_t)n + 1)),
                      "alloc lens")) ||
-      (s = check_hip(hipMalloc((void**)&w->order, sizeof(uint32_t) * n), "alloc order")) ||
-      (s = check_hip(hipMalloc((void**)&w->hist, sizeof(uint32_t) * nb), "alloc hist")) ||
-      (s = check_hip(hipMalloc((void**)&w->ctr, sizeof(uint32_t)), "alloc counter")) ||
-      (s = check_hip(hipMalloc((void**)&w->partial, sizeof(int4) * partial_cap), "alloc partial")))
+      (s = check_hip(dev_malloc((void**)&w->order, sizeof(uint32_t) * n), "alloc order")) ||
+      (s = check_hip(dev_malloc((void**)&w->hist, sizeof(uint32_t) * nb), "alloc hist")) ||
+      (s = check_hip(dev_malloc((void**)&w->ctr, sizeof(uint32_t)), "alloc counter")) ||
+      (s = check_hip(dev_malloc((void**)&w->partial, sizeof(int4) * partial_cap), "alloc partial")))
     return s;
   if (qual_mode(ix) &&
-      (s = check_hip(hipMalloc((void**)&w->er.qsc, sizeof(uint16_t) * ((uint64_t)n * w->er.mstride + 64)),
+      (s = check_hip(dev_malloc((void**)&w->er.qsc, sizeof(uint16_t) * ((uint64_t)n * w->er.mstride + 64)),
                      "alloc position scores")))
     return s;
   if ((ix->p.flags & MAXSS_EXCLUDE_ADJACENT) &&
-      ((s = check_hip(hipMalloc((void**)&w->excl, sizeof(int32_t) * n), "alloc excl")) ||
-       (s = check_hip(hipMalloc((void**)&w->lens2, sizeof(uint32_t) * n), "alloc lens2")) ||
-       (s = check_hip(hipMalloc((void**)&w->again, sizeof(maxss_top2) * n), "alloc again"))))
+      ((s = check_hip(dev_malloc((void**)&w->excl, sizeof(int32_t) * n), "alloc excl")) ||
+       (s = check_hip(dev_malloc((void**)&w->lens2, sizeof(uint32_t) * n), "alloc lens2")) ||
+       (s = check_hip(dev_malloc((void**)&w->again, sizeof(maxss_top2) * n), "alloc again"))))
     return s;
   return MAXSS_OK;
 }
@@ -1522,7 +1522,7 @@ extern "C" maxss_status maxss_scan_reads(const maxss_index* index, const maxss_r
     if ((s = alloc_scan_work(ix, n, scan_partial_entries(ix, n, nullptr), true, st, &w))) break;
     if (reads->on_device) {
       dout = out;
-    } else if ((s = check_hip(hipMallocAsync((void**)&dout, sizeof(maxss_top2) * n, st),
+    } else if ((s = check_hip(dev_malloc_async((void**)&dout, sizeof(maxss_top2) * n, st),
                               "alloc out"))) {
       break;
     }
