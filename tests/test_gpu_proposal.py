@@ -447,3 +447,60 @@ def test_train_step_rejects_bad_candidate_ids(small):
     assert e.value.status == mx.MAXSS_EINVAL
     assert (m.params() == gen.mlp_init(12)).all()
     m.close()
+
+
+@pytest.mark.parametrize("mode", ["plain", "exclude-adjacent", "fast"])
+def test_guarded_scan_decisions_and_records(small, mode):
+    """The exact-score guard: with margin tau = +inf a read keeps its
+    candidate record exactly when the best candidate's exact score (the
+    oracle's value, max over the candidate set) reaches min_score; every kept
+    read carries the oracle's top-2 among its candidates (with the neighbour
+    exclusion: the best candidate other than the best one's neighbours) and
+    every other read the oracle's full-scan record.  Margin and score rule
+    together: a read is kept when either holds."""
+    torch = _torch()
+    g, r, _ = small
+    lf, of = {"plain": (0, 0), "exclude-adjacent": (mx.MAXSS_EXCLUDE_ADJACENT, oracle.EXCL_ADJ),
+              "fast": (mx.MAXSS_FAST, oracle.FAST)}[mode]
+    ix = mx.Index(g.seq, 2048, 150, flags=lf)
+    m = mx.Model(seed=0, init=mx.MAXSS_INIT_PROFILE_MATCH)
+    K = 8
+    s, o = _dev_reads(torch, r)
+    cand = torch.zeros(r.n * K, dtype=torch.int32, device="cuda")
+    mg = torch.zeros(r.n, dtype=torch.float32, device="cuda")
+    fb0 = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+    m.candidates(ix, s, o, K, 0.0, cand, mg, fb0)
+    torch.cuda.synchronize()
+    cand = cand.cpu().numpy().reshape(r.n, K)
+    mg = mg.cpu().numpy()
+    full = oracle.scan(g.seq, 2048, r.seq, r.offsets, flags=of, nthreads=8)
+    _, vals = oracle.scan(g.seq, 2048, r.seq, r.offsets, flags=of & ~oracle.EXCL_ADJ, nthreads=8,
+                          want_values=True)
+    best = np.array([max(int(vals[i][f]) for f in cand[i] if f >= 0) for i in range(r.n)])
+    ms = int(np.median(best))
+    tau_mid = float(np.median(mg))
+    for tau in (float("inf"), tau_mid):
+        out = torch.zeros(r.n * 32, dtype=torch.uint8, device="cuda")
+        fb = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+        m.scan(ix, s, o, K, tau, out, fb, min_score=ms)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+        fb = fb.cpu().numpy()
+        keep = (best >= ms) | (mg >= tau)
+        assert (fb == ~keep).all(), (tau, np.nonzero(fb != ~keep)[0][:5])
+        assert 0 < keep.sum() < r.n
+        for i in range(r.n):
+            if not keep[i]:
+                for f in ("frag", "score", "offset", "strand"):
+                    assert (got[f][i] == full[f][i]).all(), (mode, tau, i)
+                continue
+            c = [int(f) for f in cand[i] if f >= 0]
+            f1, s1, f2, s2 = mlp.top2_among(vals[i], c)
+            if mode == "exclude-adjacent":
+                rest = [f for f in c if abs(f - f1) > 1]
+                f2, _, _, _ = mlp.top2_among(vals[i], rest) if rest else (-1, -1, -1, -1)
+                s2 = int(vals[i][f2]) if f2 >= 0 else -1
+            assert got["frag"][i].tolist() == [f1, f2], (mode, tau, i)
+            assert got["score"][i].tolist() == [s1, s2], (mode, tau, i)
+    m.close()
+    ix.close()
