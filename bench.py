@@ -17,8 +17,9 @@ Beside the step, on the same reads: the scan of host buffers (PCIe
 included), MaxSSmap_fast, base-quality scoring, the neighbour exclusion of
 the second-best fragment and the learned proposal against the full scan;
 then the batched path on the 248 Mbp chromosome-scale workload (persistent
-scan, captured graph, autotuned tiles; one eager and one timed graph step)
-and the CPU oracle on samples (each leg can be switched off).
+scan, captured graph, autotuned tiles; one eager and one timed graph step),
+the damaged short reads on that genome (one eager plan step) and the CPU
+oracle on samples (each leg can be switched off).
 
 Prints one JSON line.  `--gpus N` with N > 1 is refused: the benchmark
 measures one GPU (the scan shards by reads across GPUs with no collective).
@@ -417,12 +418,15 @@ def scan_roofline(cells: float, scan_s: float, kind: int, knp: int, workload: st
     return r
 
 
-def batched_run(name: str, args, steps: int, dev, measured_peak, budget_s: float):
+def batched_run(name: str, args, steps: int, dev, measured_peak, budget_s: float,
+                tune_tiles: bool = True):
     """The batched path on a chromosome-scale workload: one persistent scan
     launch per mixed-length batch, replayed from a captured HIP graph, tiles
-    from the autotuner (parity-gated).  One eager step with kernel events
-    (also the warm-up), then up to `steps` graph steps, fewer when they would
-    take more than budget_s; the first graph step includes the capture."""
+    from the autotuner (parity-gated) unless tune_tiles is False.  One eager
+    step with kernel events (also the warm-up), then up to `steps` graph
+    steps, fewer when they would take more than budget_s; the first graph
+    step includes the capture.  With steps = 0 the eager step is the timed
+    one."""
     import numpy as np
     import torch
 
@@ -441,9 +445,11 @@ def batched_run(name: str, args, steps: int, dev, measured_peak, budget_s: float
     cig = torch.empty(n * stride, dtype=torch.uint8, device=dev)
     cells = 2.0 * w.genome.G * float(w.reads.lengths().sum())
     t1 = time.time()
-    sample = w.reads.subset(np.arange(0, n, max(1, n // args.tune_sample))[:args.tune_sample])
-    tune = ix.autotune(sample.seq, sample.offsets)
-    log("%s: autotune %.1fs %s" % (name, time.time() - t1, tune))
+    tune = None
+    if tune_tiles and args.tune_sample > 0:
+        sample = w.reads.subset(np.arange(0, n, max(1, n // args.tune_sample))[:args.tune_sample])
+        tune = ix.autotune(sample.seq, sample.offsets)
+        log("%s: autotune %.1fs %s" % (name, time.time() - t1, tune))
     plan = mx.Plan(ix, capacity=n, pad=w.pad, cigar_stride=stride)
     stream = torch.cuda.Stream()
 
@@ -461,7 +467,7 @@ def batched_run(name: str, args, steps: int, dev, measured_peak, budget_s: float
     other = {k: mx.maxss_profile_read(k) for k in ("encode", "merge", "rescan")}
     mx.maxss_profile_enable(False)
     log("%s: eager step %.1fs, scan kernel %.1f ms" % (name, t_eager, scan_ms))
-    k = max(1, min(steps, int(budget_s / max(t_eager, 1e-3))))
+    k = max(1, min(steps, int(budget_s / max(t_eager, 1e-3)))) if steps > 0 else 0
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     for i in range(k):
@@ -469,6 +475,8 @@ def batched_run(name: str, args, steps: int, dev, measured_peak, budget_s: float
         torch.cuda.synchronize()
         log("%s: timed graph step %d done" % (name, i))
     dt = time.perf_counter() - t3
+    if k == 0:
+        k, dt = 1, t_eager
     knp, kind = ix.kernel_info()
     scan_s = scan_ms / max(scan_k, 1) / 1e3
     res = {"workload": "%s: %d bp genome, F=%d (%d fragments), %d reads, lengths %d-%d, both "
@@ -482,7 +490,9 @@ def batched_run(name: str, args, steps: int, dev, measured_peak, budget_s: float
            "scan_ms_per_launch": round(scan_s * 1e3, 3),
            "nw_ms_per_launch": round(nw_ms / max(nw_k, 1), 3),
            "other_ms": {kk: round(v[0] / max(v[1], 1), 3) for kk, v in other.items()},
-           "step_path": "plan + hipGraph replay (capture in the first timed step), autotuned tiles",
+           "step_path": ("plan + hipGraph replay (capture in the first timed step)" if steps > 0
+                         else "plan, one eager step with kernel events")
+                        + (", autotuned tiles" if tune is not None else ", built-in tiles"),
            "autotune": tune,
            "roofline": scan_roofline(cells, scan_s, kind, knp, name, measured_peak)}
     plan.close()
@@ -513,6 +523,8 @@ def main():
                          "second-best")
     ap.add_argument("--no-chromosome", action="store_true",
                     help="skip the chromosome-scale batched leg of the default run")
+    ap.add_argument("--no-damaged", action="store_true",
+                    help="skip the damaged-read leg (one eager step) of the default run")
     ap.add_argument("--batched-budget", type=float, default=60.0,
                     help="seconds of timed graph steps on a chromosome-scale workload (the "
                          "step count is lowered to fit)")
@@ -664,6 +676,12 @@ def main():
         # the batched path at chromosome scale: one eager and one graph step
         bres, _ = batched_run("chromosome", args, 1, dev, measured_peak, args.batched_budget)
         res["chromosome"] = bres
+    if not args.no_damaged and w.name == "bacterial":
+        # the damaged short reads on the same genome: one eager plan step,
+        # built-in tiles
+        dres, _ = batched_run("damaged", args, 0, dev, measured_peak, args.batched_budget,
+                              tune_tiles=False)
+        res["damaged"] = dres
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

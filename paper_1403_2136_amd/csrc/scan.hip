@@ -1060,24 +1060,35 @@ __global__ __launch_bounds__(256) void rescan_kernel(
     }
   }
   __syncthreads();
+  // The fragment's value is known (the merge wrote it): windows are taken
+  // in (strand, offset) order, a block-wide chunk at a time, and the scan
+  // stops after the first chunk in which some window reaches the value (the
+  // smallest such window lies there, every later one is larger).
+  const int target = out[i].score[which];
   uint64_t best = 0;
-  for (uint32_t s = 0; s < nstrands; s++) {
+  bool done = false;
+  for (uint32_t s = 0; s < nstrands && !done; s++) {
     const uint8_t* q = lq + s * m;
-    for (uint32_t o = threadIdx.x; o < F; o += blockDim.x) {
-      int H = 0, B = 0;
-      for (uint32_t k = 0; k < m; k += STEP) {
-        const uint8_t g = lg[o + k], c = q[k];
-        if constexpr (QS) {
-          const uint16_t v = lp[s * m + k];
-          H += (g == c && c != kN) ? (int)(int8_t)(v & 0xFFu) : (int)(int8_t)(v >> 8);
-        } else {
-          H += (g == c && c != kN) ? M : X;
+    for (uint32_t o0 = 0; o0 < F && !done; o0 += blockDim.x) {
+      const uint32_t o = o0 + threadIdx.x;
+      int H = 0, B = -1;
+      if (o < F) {
+        B = 0;
+        for (uint32_t k = 0; k < m; k += STEP) {
+          const uint8_t g = lg[o + k], c = q[k];
+          if constexpr (QS) {
+            const uint16_t v = lp[s * m + k];
+            H += (g == c && c != kN) ? (int)(int8_t)(v & 0xFFu) : (int)(int8_t)(v >> 8);
+          } else {
+            H += (g == c && c != kN) ? M : X;
+          }
+          H = max(H, 0);
+          B = max(B, H);
         }
-        H = max(H, 0);
-        B = max(B, H);
+        const uint64_t key = ((uint64_t)(uint32_t)B << 32) | (0xFFFFFFFFu - (s * F + o));
+        best = key > best ? key : best;
       }
-      const uint64_t key = ((uint64_t)(uint32_t)B << 32) | (0xFFFFFFFFu - (s * F + o));
-      best = key > best ? key : best;
+      done = __syncthreads_or(B == target) != 0;
     }
   }
   // block max of the 64-bit keys
