@@ -334,13 +334,25 @@ def fast_leg(w, seq, off, top_full, full_scan_ms, stream):
 def qual_leg(w, seq, off, full_scan_ms, stream, scale: int = 10):
     """Base-quality scoring (position-specific scores from synthetic Phred
     qualities at 1/scale resolution): scan time against the plain scan's on
-    the same reads."""
+    the same reads, and the share of reads whose bases all map to one
+    (match, mismatch) pair (the register-bank launch of the quality split;
+    the others take the position-specific kernel)."""
     import numpy as np
     import torch
 
     import gen
     import paper_1403_2136_amd as mx
-    q = torch.from_numpy(gen.sample_qualities(w.reads, 91)).cuda()
+    qh = gen.sample_qualities(w.reads, 91)
+    q = torch.from_numpy(qh).cuda()
+    # the score table's rule: x = 1 - 10^(-Q/10), pair = (round(M x scale),
+    # round(X x scale / 3)), halves away from zero
+    x = 1.0 - 10.0 ** (-(qh.astype(np.float64) - 33) / 10.0)
+    rnd = lambda v: np.sign(v) * np.floor(np.abs(v) + 0.5)
+    pair = rnd(w.M * x * scale) * 256 + rnd(w.X * x * scale / 3.0)
+    starts = w.reads.offsets[:-1].astype(np.int64)
+    first = np.repeat(pair[starts], w.reads.lengths().astype(np.int64))
+    diff = np.add.reduceat((pair != first).astype(np.int64), starts)
+    one_pair = float((diff == 0).mean())
     ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap, qual_scale=scale)
     n = w.reads.n
     out = torch.empty(n * 32, dtype=torch.uint8, device="cuda")
@@ -356,7 +368,8 @@ def qual_leg(w, seq, off, full_scan_ms, stream, scale: int = 10):
     res = {"qual_scale": scale, "scan_ms_per_launch": round(ms / max(k, 1), 3),
            "plain_scan_ms_per_launch": round(full_scan_ms, 3),
            "gcups_kernel": round(cells / (ms / max(k, 1) / 1e3) / 1e9, 1),
-           "slowdown": round((ms / max(k, 1)) / full_scan_ms, 3)}
+           "slowdown": round((ms / max(k, 1)) / full_scan_ms, 3),
+           "reads_with_one_score_pair": round(one_pair, 4)}
     log("qual: %s" % res)
     return res
 

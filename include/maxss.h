@@ -297,7 +297,10 @@ maxss_status maxss_autotune(maxss_index* index, const maxss_reads* sample, const
  *   REGISTER_BANK  the four per-base score pairs of every window word kept
  *                  in registers (one v_perm_b32 each when the word enters):
  *                  add, half a max, a quarter of a select: 1.75
- *                  (16 offsets pairs per lane, plain scores). */
+ *                  (16 offsets pairs per lane).  With base-quality scores
+ *                  it takes the reads whose scored bases all map to one
+ *                  (match, mismatch) pair, each read with its own pair; a
+ *                  second launch of TWO_STEP takes the other reads. */
 #define MAXSS_KERNEL_STEP_MAX 0
 #define MAXSS_KERNEL_TWO_STEP 1
 #define MAXSS_KERNEL_REGISTER_BANK 2

@@ -103,7 +103,19 @@ struct ScanArgs {
   const uint16_t* qsc;  // quality mode: [n][mp_max] (match | mismatch << 8) per position
   uint32_t cq;          // LDS words of position-score pairs per read strand
   const int32_t* excl;  // NULL, or per read a fragment e: e-1, e, e+1 never enter its top-2
+  // quality mode, one of two launches: 1 takes the reads whose positions all
+  // share one (match, mismatch) pair, 2 the others; 0: every read
+  uint32_t qsplit;
 };
+
+// The all-mismatch score pool of mismatch score x (int8): bytes
+// [X, X, sign(X), X, 0, X, 0, X].
+__host__ __device__ inline uint64_t mismatch_pool(uint32_t x8) {
+  x8 &= 0xFFu;
+  const uint64_t sx = (x8 & 0x80u) ? 0xFFull : 0ull;
+  return (uint64_t)x8 | ((uint64_t)x8 << 8) | (sx << 16) | ((uint64_t)x8 << 24) |
+         ((uint64_t)x8 << 40) | ((uint64_t)x8 << 56);
+}
 
 template <int NP>
 __device__ inline uint32_t staged_words(uint32_t mp) {
@@ -719,7 +731,23 @@ __device__ inline int wave_max_i32(int v) {
   return v;
 }
 
-template <int NP, bool QS, bool WIDE, bool BANK>
+// Whether every scored position of read `rid` (length L) has the pair of
+// its first position, and that pair.
+__device__ inline bool one_pair(const uint16_t* __restrict__ qsc, uint32_t mp_max, uint32_t rid,
+                                uint32_t L, uint32_t& pair) {
+  const uint16_t* qr = qsc + (uint64_t)rid * mp_max;
+  pair = L ? qr[0] : 0u;
+  const uint32_t two = pair * 0x10001u;
+  const uint32_t* q2 = reinterpret_cast<const uint32_t*>(qr);  // rows are 128-byte aligned
+  bool one = true;
+  for (uint32_t k = 0; k < L / 2; k++) one &= q2[k] == two;
+  if (L & 1) one &= qr[L - 1] == pair;
+  return one;
+}
+
+// QB: the register-bank kernel of the quality split (qsplit 1), each read
+// scored with its own pair as plain scores.
+template <int NP, bool QS, bool WIDE, bool BANK, bool QB = false>
 __device__ __forceinline__ void scan_body(const ScanArgs& a) {
   extern __shared__ uint32_t lds[];
   constexpr uint32_t HALF = 64u * NP, S = 128u * NP;
@@ -744,7 +772,17 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
     const uint32_t my_read = lane < rcount ? a.order[rbase + lane] : 0u;
     // Kadane steps of the read: its length, or half of it rounded up when
     // every other base is scored
-    const uint32_t my_len = lane < rcount ? (a.lens[my_read] + a.step - 1) / a.step : 0u;
+    uint32_t my_len = lane < rcount ? (a.lens[my_read] + a.step - 1) / a.step : 0u;
+    // quality split: this launch's reads only (a read of the other kind is
+    // skipped like an empty one, and its record is the other launch's)
+    uint32_t my_pair = 0;
+    bool mine = true;
+    if (QB || (QS && a.qsplit)) {
+      if (lane < rcount) {
+        mine = one_pair(a.qsc, a.mp_max, my_read, a.lens[my_read], my_pair) == QB;
+        if (!mine) my_len = 0;
+      }
+    }
     const uint32_t my_mp = (my_len + NP - 1) / NP * NP;
     const uint32_t mp_tile = (uint32_t)wave_max_i32((int)my_mp);
     const uint32_t nwords = staged_words<NP>(mp_tile);
@@ -829,8 +867,16 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
           for (uint32_t s = 0; s < a.nstrands; s++) {
             s16x2 B[NP];
             if constexpr (BANK) {
-              kadane_pairs_bank(lds, lane, lcodes + (r * 2 + s) * a.cw, m, a.xpool, a.dpool,
-                                xx);
+              uint64_t xp = a.xpool, dp = a.dpool;
+              uint32_t x2 = xx;
+              if constexpr (QB) {
+                // the read's pair: match in the low byte, mismatch in the high
+                const uint32_t pr = __builtin_amdgcn_readlane(my_pair, r);
+                xp = mismatch_pool(pr >> 8);
+                dp = (pr ^ (pr >> 8)) & 0xFFu;
+                x2 = (uint32_t)(uint16_t)(int16_t)(int8_t)(pr >> 8) * 0x10001u;
+              }
+              kadane_pairs_bank(lds, lane, lcodes + (r * 2 + s) * a.cw, m, xp, dp, x2);
               if (!partial_seg) {
                 bm = bank_fold(bm);
                 continue;
@@ -869,7 +915,8 @@ __device__ __forceinline__ void scan_body(const ScanArgs& a) {
         }
       }
     }
-    if (lane < rcount) a.partial[(uint64_t)my_read * a.nchunks + chunk] = make_int4(t1s, t1f, t2s, t2f);
+    if (lane < rcount && mine)
+      a.partial[(uint64_t)my_read * a.nchunks + chunk] = make_int4(t1s, t1f, t2s, t2f);
   }
 }
 
@@ -883,6 +930,12 @@ __global__ __launch_bounds__(64) void scan_kernel(ScanArgs a) {
 __global__ __launch_bounds__(64) __attribute__((amdgpu_num_vgpr(32))) void scan_kernel_bank(
     ScanArgs a) {
   scan_body<16, false, false, true>(a);
+}
+
+// The same kernel for the quality split's reads with one score pair.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_num_vgpr(32))) void scan_kernel_bank_qual(
+    ScanArgs a) {
+  scan_body<16, false, false, true, true>(a);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint32_t n) {
@@ -1111,6 +1164,7 @@ struct Tiles {
   int NP;
   bool qs;                 // quality mode (position-specific scores)
   bool wide;               // scores may pass 31744: per-step max for B
+  bool qb;                 // the register-bank launch of the quality split
   uint32_t R, ntiles, nchunks, nseg, grid;
   uint32_t win_slots, cw, cq;
   size_t lds;
@@ -1127,7 +1181,8 @@ static const void* scan_fn_np(int NP) {
   return (const void*)scan_kernel<32, QS, WIDE>;
 }
 
-static const void* scan_fn(int NP, bool qs, bool wide) {
+static const void* scan_fn(int NP, bool qs, bool wide, bool qb = false) {
+  if (qb) return (const void*)scan_kernel_bank_qual;
   if (qs) return wide ? scan_fn_np<true, true>(NP) : scan_fn_np<true, false>(NP);
   return wide ? scan_fn_np<false, true>(NP) : scan_fn_np<false, false>(NP);
 }
@@ -1147,14 +1202,15 @@ static void launch_qw(int NP, const ScanArgs& a, uint32_t grid, size_t lds, hipS
 
 static maxss_status launch_scan(const Tiles& t, const ScanArgs& a, hipStream_t st) {
   if (t.lds > 65536) {
-    maxss_status s = check_hip(hipFuncSetAttribute(scan_fn(t.NP, t.qs, t.wide),
+    maxss_status s = check_hip(hipFuncSetAttribute(scan_fn(t.NP, t.qs, t.wide, t.qb),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    (int)t.lds),
                                "hipFuncSetAttribute(scan_kernel)");
     if (s) return s;
   }
-  ProfScope prof("scan", st);
-  if (t.qs) {
+  if (t.qb) {
+    scan_kernel_bank_qual<<<t.grid, 64, t.lds, st>>>(a);
+  } else if (t.qs) {
     if (t.wide) launch_qw<true, true>(t.NP, a, t.grid, t.lds, st);
     else launch_qw<true, false>(t.NP, a, t.grid, t.lds, st);
   } else {
@@ -1167,16 +1223,16 @@ static maxss_status launch_scan(const Tiles& t, const ScanArgs& a, hipStream_t s
 // Resident scan waves per CU for (kernel instance, LDS bytes), queried once
 // per shape and cached, so that a step being captured into a graph makes no
 // runtime query.
-static int occupancy_for(int NP, bool qs, bool wide, size_t lds) {
+static int occupancy_for(int NP, bool qs, bool wide, size_t lds, bool qb = false) {
   static std::mutex mu;
   static std::map<std::pair<int, size_t>, int> cache;
   std::lock_guard<std::mutex> g(mu);
-  const int key = NP * 4 + (qs ? 2 : 0) + (wide ? 1 : 0);
+  const int key = NP * 8 + (qb ? 4 : 0) + (qs ? 2 : 0) + (wide ? 1 : 0);
   auto it = cache.find({key, lds});
   if (it != cache.end()) return it->second;
   int blocks = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_fn(NP, qs, wide), 64, lds);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, scan_fn(NP, qs, wide, qb), 64, lds);
   if (e != hipSuccess || blocks < 1) blocks = 1;
   cache[{key, lds}] = blocks;
   return blocks;
@@ -1198,8 +1254,9 @@ static constexpr size_t kScanLdsBudget = 40 * 1024;
 static int np_for(const Index* ix, const TileOverride* force) {
   const uint32_t F = ix->F;
   if (force && (force->NP == 8 || force->NP == 16 || force->NP == 32)) return force->NP;
-  // plain scores within the narrow bound: NP = 16 runs the register-bank kernel
-  if (F % 2048 == 0 && !qual_mode(ix) && score_bound(ix) <= kNarrowScoreMax) return 16;
+  // scores within the narrow bound: NP = 16 runs the register-bank kernel
+  // (in quality mode for the reads whose positions share one score pair)
+  if (F % 2048 == 0 && score_bound(ix) <= kNarrowScoreMax) return 16;
   if (F % 4096 == 0) return 32;
   if (F % 2048 == 0) return 16;
   return 8;
@@ -1209,6 +1266,24 @@ static int np_for(const Index* ix, const TileOverride* force) {
 // tiles of R reads (bounded by the LDS budget) and a fragment-chunk count
 // that fills whole rounds of the resident waves.  partial_cap (0 = none)
 // bounds reads x chunks, the size of the per-chunk top-2 buffer.
+// Most reads per tile (a power of two up to 32) whose LDS fits the per-wave
+// budget of kernel (NP, qs, wide, qb): at most kScanLdsBudget, and no more
+// than lets every wave that the kernel's registers allow stay resident on a
+// CU.
+static uint32_t rmax_for(const Index* ix, const Tiles& t, size_t win_bytes, size_t per_read) {
+  size_t budget = kScanLdsBudget;
+  const int reg_waves = occupancy_for(t.NP, t.qs, t.wide, 0, t.qb);
+  if (ix->lds_per_cu && reg_waves > 0 && ix->lds_per_cu / (size_t)reg_waves < budget)
+    budget = ix->lds_per_cu / (size_t)reg_waves;
+  uint32_t rmax = 32;
+  while (rmax > 1 && win_bytes + rmax * per_read > budget) rmax /= 2;
+  if (win_bytes + rmax * per_read > 64 * 1024 && rmax > 1) rmax = 1;
+  return rmax;
+}
+
+// In quality mode with NP = 16 and narrow scores the scan is split in two
+// launches (scan_core): the shape chosen here is the register-bank launch's
+// (qb), and split_second() derives the position-specific launch's.
 static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
                           const TileOverride* force, uint64_t partial_cap) {
   if (!force) force = &ix->tune;
@@ -1220,23 +1295,19 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
   t.cw = mstride / 8 + (uint32_t)t.NP / 8 + 1;
   t.qs = qual_mode(ix);
   t.wide = score_bound(ix) > kNarrowScoreMax;
+  if (t.qs && t.NP == 16 && !t.wide) {
+    t.qs = false;
+    t.qb = true;
+  }
   if (t.NP == 16 && !t.qs && !t.wide) t.cw *= 2;  // register banks: code bytes
   t.cq = t.qs ? (mstride / scan_step(ix) + 1) / 2 + 1 : 0u;
   const size_t win_bytes = (size_t)t.win_slots * 4u;
   const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
-  // LDS per wave: at most kScanLdsBudget, and no more than lets every wave
-  // that the kernel's registers allow stay resident on a CU
-  size_t budget = kScanLdsBudget;
-  const int reg_waves = occupancy_for(t.NP, t.qs, t.wide, 0);
-  if (ix->lds_per_cu && reg_waves > 0 && ix->lds_per_cu / (size_t)reg_waves < budget)
-    budget = ix->lds_per_cu / (size_t)reg_waves;
-  uint32_t rmax = 32;
-  while (rmax > 1 && win_bytes + rmax * per_read > budget) rmax /= 2;
-  if (win_bytes + rmax * per_read > 64 * 1024 && rmax > 1) rmax = 1;
+  const uint32_t rmax = rmax_for(ix, t, win_bytes, per_read);
   t.R = force->R ? (force->R < rmax ? force->R : rmax) : rmax;
   t.lds = win_bytes + t.R * per_read;
   const uint32_t resident =
-      (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.wide, t.lds);
+      (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.wide, t.lds, t.qb);
   if (!force->R)
     while (t.R > 4 && (uint64_t)((n + t.R - 1) / t.R) * ix->NF < 4ull * resident) t.R /= 2;
   t.lds = win_bytes + t.R * per_read;
@@ -1271,6 +1342,32 @@ static Tiles choose_tiles(const Index* ix, uint32_t n, uint32_t mstride,
     }
   }
   t.nchunks = best_c;
+  const uint64_t total = (uint64_t)t.ntiles * t.nchunks;
+  t.grid = (uint32_t)(total < resident ? total : resident);
+  if (t.grid < 1) t.grid = 1;
+  return t;
+}
+
+// The position-specific launch of the quality split, from the register-bank
+// launch's shape tb: the same fragment chunks (both write one record per read
+// and chunk), its own codes, position-score pairs and reads per tile (its
+// LDS budget is smaller); one read per tile in candidate mode.
+static Tiles split_second(const Index* ix, const Tiles& tb, uint32_t n, uint32_t mstride,
+                          const TileOverride* force, bool one_read) {
+  if (!force) force = &ix->tune;
+  Tiles t = tb;
+  t.qb = false;
+  t.qs = true;
+  t.cw = tb.cw / 2;
+  t.cq = (mstride / scan_step(ix) + 1) / 2 + 1;
+  const size_t win_bytes = (size_t)t.win_slots * 4u;
+  const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
+  const uint32_t rmax = rmax_for(ix, t, win_bytes, per_read);
+  t.R = one_read ? 1u : (force->R ? (force->R < rmax ? force->R : rmax) : rmax);
+  t.lds = win_bytes + t.R * per_read;
+  t.ntiles = one_read ? n : (n + t.R - 1) / t.R;
+  const uint32_t resident =
+      (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.wide, t.lds);
   const uint64_t total = (uint64_t)t.ntiles * t.nchunks;
   t.grid = (uint32_t)(total < resident ? total : resident);
   if (t.grid < 1) t.grid = 1;
@@ -1369,7 +1466,7 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
     const size_t per_read = (size_t)2 * (t.cw + t.cq) * 4u;
     t.lds = (size_t)t.win_slots * 4u + per_read;
     const uint32_t resident =
-      (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.wide, t.lds);
+      (uint32_t)ix->num_cu * (uint32_t)occupancy_for(t.NP, t.qs, t.wide, t.lds, t.qb);
     t.ntiles = n;
     uint64_t want = (8ull * resident + n - 1) / n;
     if (want < 1) want = 1;
@@ -1383,10 +1480,7 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
     return fail(MAXSS_ESTATE, "partial buffer too small (%llu < %llu)",
                 (unsigned long long)w.partial_cap, (unsigned long long)n * t.nchunks);
   const uint32_t M8 = (uint32_t)ix->p.match & 0xFFu, X8 = (uint32_t)ix->p.mismatch & 0xFFu;
-  const uint64_t sx = ix->p.mismatch < 0 ? 0xFFull : 0ull;
-  // all-mismatch pool: bytes [X, X, sign(X), X, 0, X, 0, X]
-  const uint64_t xpool = (uint64_t)X8 | ((uint64_t)X8 << 8) | (sx << 16) | ((uint64_t)X8 << 24) |
-                         ((uint64_t)X8 << 40) | ((uint64_t)X8 << 56);
+  const uint64_t xpool = mismatch_pool(X8);
   // reads ordered by length, longest first
   const uint32_t nb = ix->p.max_read_len + 1;
   fill_u32_kernel<<<(nb + 255) / 256, 256, 0, st>>>(w.hist, 0u, nb);
@@ -1406,11 +1500,37 @@ static maxss_status scan_core(const Index* ix, const EncodedReads& er, const uin
   a.nstrands = nstrands; a.mp_max = mstride;
   a.cand = cand; a.K = K; a.nfe = cand ? Kc : ix->NF;
   a.step = scan_step(ix);
-  a.qsc = t.qs ? er.qsc : nullptr;
+  const bool quality = t.qs || t.qb;
+  a.qsc = quality ? er.qsc : nullptr;
   a.cq = t.cq;
   a.excl = excl;
-  if (t.qs && !er.qsc) return fail(MAXSS_ESTATE, "quality mode without position scores");
-  s = launch_scan(t, a, st);
+  if (quality && !er.qsc) return fail(MAXSS_ESTATE, "quality mode without position scores");
+  {
+    ProfScope prof("scan", st);
+    if (t.qb) {
+      // Quality split.  A read whose scored positions all carry one (match,
+      // mismatch) pair scores exactly as plain scores with that pair, so the
+      // register-bank kernel takes those reads (each with its own pair) and
+      // the position-specific kernel the others.  Both launches take the
+      // reads in the same order and cut the fragments into the same chunks,
+      // and each writes only its own reads' chunk records, so the merge
+      // sees one complete set.
+      a.qsplit = 1;
+      if ((s = launch_scan(t, a, st))) return s;
+      const Tiles tq = split_second(ix, t, n, mstride, force, cand != nullptr);
+      ScanArgs aq = a;
+      aq.cw = tq.cw;
+      aq.cq = tq.cq;
+      aq.R = tq.R;
+      aq.ntiles = tq.ntiles;
+      aq.total_work = tq.ntiles * tq.nchunks;
+      aq.qsplit = 2;
+      fill_u32_kernel<<<1, 64, 0, st>>>(w.ctr, 0u, 1u);
+      s = launch_scan(tq, aq, st);
+    } else {
+      s = launch_scan(t, a, st);
+    }
+  }
   if (s) return s;
   {
     ProfScope prof("merge", st);
@@ -1556,10 +1676,10 @@ extern "C" maxss_status maxss_scan_kernel_info(const maxss_index* index, int32_t
   const Index* ix = reinterpret_cast<const Index*>(index);
   if (!ix) return fail(MAXSS_EINVAL, "NULL index");
   const int NP = np_for(ix, &ix->tune);
-  const bool qs = qual_mode(ix), wide = score_bound(ix) > kNarrowScoreMax;
+  const bool wide = score_bound(ix) > kNarrowScoreMax;
   if (np) *np = NP;
   if (kind)
     *kind = wide ? MAXSS_KERNEL_STEP_MAX
-                 : (NP == 16 && !qs ? MAXSS_KERNEL_REGISTER_BANK : MAXSS_KERNEL_TWO_STEP);
+                 : (NP == 16 ? MAXSS_KERNEL_REGISTER_BANK : MAXSS_KERNEL_TWO_STEP);
   return MAXSS_OK;
 }

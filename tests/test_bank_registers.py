@@ -1,8 +1,9 @@
-"""The register-bank scan kernel keeps its state in v64..v255 between asm
-statements, so the compiler's own code in that kernel must stay in v0..v63.
-This compiles the scan source to gfx950 assembly (no GPU needed) and checks
-the compiler-generated instructions of the kernel, outside the asm
-statements, against that range, and that the kernel spills no VGPRs."""
+"""The register-bank scan kernels (plain scores, and the quality split's
+reads with one score pair) keep their state in v64..v255 between asm
+statements, so the compiler's own code in them must stay in v0..v63.  This
+compiles the scan source to gfx950 assembly (no GPU needed) and checks the
+compiler-generated instructions of each kernel, outside the asm statements,
+against that range, and that the kernels spill no VGPRs."""
 import os
 import re
 import subprocess
@@ -12,7 +13,8 @@ import pytest
 
 from paper_1403_2136_amd import build as b
 
-KERNEL = "_ZN5maxss16scan_kernel_bankENS_8ScanArgsE"
+KERNELS = ["_ZN5maxss16scan_kernel_bankENS_8ScanArgsE",
+           "_ZN5maxss21scan_kernel_bank_qualENS_8ScanArgsE"]
 
 
 def _vgprs(line):
@@ -23,7 +25,7 @@ def _vgprs(line):
 
 
 @pytest.fixture(scope="module")
-def kernel_asm():
+def scan_asm():
     if not os.path.exists(b.HIPCC):
         pytest.skip("hipcc not available")
     with tempfile.TemporaryDirectory() as d:
@@ -32,10 +34,15 @@ def kernel_asm():
                                      os.path.join(b.CSRC, "scan.hip"), "-o", out]
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr[-2000:]
-        text = open(out).read()
-    start = text.index(KERNEL + ":")
+        return open(out).read()
+
+
+@pytest.fixture(params=KERNELS, ids=["plain", "quality"])
+def kernel_asm(scan_asm, request):
+    text, kernel = scan_asm, request.param
+    start = text.index(kernel + ":")
     end = text.index(".Lfunc_end", start)
-    name = text.index(".name:           " + KERNEL)
+    name = text.index(".name:           " + kernel)
     meta = text[text.rindex("- .agpr_count", 0, name):name + 600]
     return text[start:end], meta
 

@@ -201,3 +201,141 @@ def test_quality_longest_reads():
     assert ix.kernel_info()[1] == mx.MAXSS_KERNEL_STEP_MAX
     assert_same(ix.scan(rs, off, qual=qq), ref, "7168-base reads")
     ix.close()
+
+
+def _split_case(seed=101):
+    """Reads of both launches of the quality split side by side in the same
+    tiles: bases at Phred >= 20 (one score pair at scale 10), reads with one
+    Phred-2 base or several Phred-0 bases (several pairs), reads entirely at
+    Phred 2 or entirely at 0 (one pair, another than the common one), reads
+    with N, lengths 1..250, a genome with N runs."""
+    g = gen.with_n_runs(gen.uniform_genome(41_000, seed), seed + 1, 12, 1, 80)
+    r = gen.sample_reads(g, 150, seed + 2, [1, 2, 17, 64, 100, 111, 250], 0.0, 0.3, indel_max=2)
+    q = np.maximum(gen.sample_qualities(r, seed + 3), ord("!") + 20)
+    st = gen.Stream(seed, "q.split")
+    kind = st.integers(0, 5, r.n)
+    pos = st.uniform(r.n)
+    seq = r.seq.copy()
+    for i in range(r.n):
+        a, b = int(r.offsets[i]), int(r.offsets[i + 1])
+        if kind[i] == 1:
+            q[a + int(pos[i] * (b - a))] = ord("#")
+        elif kind[i] == 2:
+            q[a:b:7] = ord("!")
+        elif kind[i] == 3:
+            q[a:b] = ord("#")
+        elif kind[i] == 4:
+            q[a:b] = ord("!")
+        if i % 9 == 0 and b - a > 4:
+            seq[a + 2] = ord("N")
+    reads = gen.Reads(seq, r.offsets, r.start, r.span, r.strand, r.rate, r.n_indel)
+    return g.seq, reads, q
+
+
+def _one_pair(r, q):
+    """Reads whose bases all map to one (match, mismatch) pair (match 5,
+    mismatch -4, scale 10: Phred >= 20 gives (50, -13), 2 gives (18, -5), 0
+    gives (0, 0); the case holds no other Phred values)."""
+    cls = np.minimum(q.astype(np.int64) - 33, 20)
+    out = np.zeros(r.n, bool)
+    for i in range(r.n):
+        c = cls[int(r.offsets[i]):int(r.offsets[i + 1])]
+        out[i] = c.size == 0 or (c == c[0]).all()
+    return out
+
+
+@pytest.mark.parametrize("F", [2048, 3072, 4096])
+def test_quality_split_both_launches_every_shape(F):
+    """The quality split (register banks for reads with one score pair, the
+    position-specific kernel for the others) against the oracle, with
+    forced tiles (NP = 16 splits; 8 and 32 do not) and the built-in ones."""
+    seq, r, q = _split_case()
+    one = _one_pair(r, q)
+    assert 0.3 < one.mean() < 0.8
+    ref = oracle.scan(seq, F, r.seq, r.offsets, M, X, nthreads=8, quals=q, qscale=QS)
+    ix = mx.Index(seq, F, 250, M, X, GAP, qual_scale=QS)
+    if F % 2048 == 0:
+        assert tuple(ix.kernel_info()) == (16, mx.MAXSS_KERNEL_REGISTER_BANK)
+    for np_, R in ((16, 8), (16, 32), (16, 1), (8, 16), (32, 16), (0, 0)):
+        if 128 * np_ > F:
+            continue
+        mx.maxss_index_set_tiles(ix.handle, np_, R, 8)
+        assert_same(ix.scan(r.seq, r.offsets, qual=q), ref, "F=%d NP=%d R=%d" % (F, np_, R))
+    mx.maxss_index_set_tiles(ix.handle, 0, 0, 0)
+    ix.close()
+
+
+def test_quality_split_flags_device_reads_and_graph():
+    """The split with the fast scan, one strand and the neighbour exclusion;
+    device reads through a plan replayed from its graph; second phase."""
+    torch = _torch()
+    seq, r, q = _split_case(131)
+    for flags, oflags in [(mx.MAXSS_FAST, oracle.FAST), (mx.MAXSS_ONE_STRAND, oracle.ONE_STRAND),
+                          (mx.MAXSS_EXCLUDE_ADJACENT, oracle.EXCL_ADJ)]:
+        ref = oracle.scan(seq, 2048, r.seq, r.offsets, M, X, flags=oflags, nthreads=8, quals=q,
+                          qscale=QS)
+        ix = mx.Index(seq, 2048, 250, M, X, GAP, flags=flags, qual_scale=QS)
+        assert_same(ix.scan(r.seq, r.offsets, qual=q), ref, "flags %d" % flags)
+        ix.close()
+    ref = oracle.scan(seq, 2048, r.seq, r.offsets, M, X, nthreads=8, quals=q, qscale=QS)
+    ix = mx.Index(seq, 2048, 250, M, X, GAP, qual_scale=QS)
+    plan = mx.Plan(ix, capacity=r.n, pad=50, cigar_stride=512)
+    s = torch.from_numpy(np.array(r.seq)).cuda()
+    o = torch.from_numpy(r.offsets.astype(np.int64)).cuda()
+    qd = torch.from_numpy(q).cuda()
+    top = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    aln = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    cig = torch.zeros(r.n * 512, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            plan.run(s, o, top, aln, cig, stream=stream, graph=True, qual=qd)
+        stream.synchronize()
+        assert_same(top.cpu().numpy().view(mx.TOP2_DTYPE), ref, "graph replay %d" % rep)
+    exp = oracle.align_top(seq, 2048, r.seq, r.offsets, ref, 50, M, X, GAP, quals=q, qscale=QS)
+    a = aln.cpu().numpy().view(mx.ALN_DTYPE)
+    assert [int(x) for x in a["score"]] == [e["score"] for e in exp]
+    plan.close()
+    ix.close()
+
+
+def test_quality_split_candidate_scan():
+    """The proposal's candidate scan on a quality index (both launches, one
+    read per tile): a read that keeps its candidates carries the exact top-2
+    among them, a read that falls back the full scan's record."""
+    torch = _torch()
+    from oracle import mlp
+    seq, r, q = _split_case(151)
+    ix = mx.Index(seq, 2048, 250, M, X, GAP, qual_scale=QS)
+    m = mx.Model(gen.mlp_init(9))
+    K = 4
+    s = torch.from_numpy(np.array(r.seq)).cuda()
+    o = torch.from_numpy(r.offsets.astype(np.int64)).cuda()
+    qd = torch.from_numpy(q).cuda()
+    out = torch.zeros(r.n * 32, dtype=torch.uint8, device="cuda")
+    fb = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+    cand = torch.zeros(r.n * K, dtype=torch.int32, device="cuda")
+    mg = torch.zeros(r.n, dtype=torch.float32, device="cuda")
+    fb2 = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+    m.candidates(ix, s, o, K, 0.0, cand, mg, fb2)
+    torch.cuda.synchronize()
+    tau = float(np.median(mg.cpu().numpy()))
+    m.scan(ix, s, o, K, tau, out, fb, qual=qd)
+    m.candidates(ix, s, o, K, tau, cand, mg, fb2)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    fb, cand = fb.cpu().numpy(), cand.cpu().numpy().reshape(r.n, K)
+    assert 0 < fb.sum() < r.n
+    full, vals = oracle.scan(seq, 2048, r.seq, r.offsets, M, X, nthreads=8, want_values=True,
+                             quals=q, qscale=QS)
+    lens = np.diff(r.offsets.astype(np.int64))
+    for i in range(r.n):
+        if fb[i]:
+            for f in FIELDS:
+                assert (got[f][i] == full[f][i]).all(), i
+            continue
+        f1, s1, f2, s2 = mlp.top2_among(vals[i], cand[i])
+        assert got["frag"][i].tolist() == [f1, f2] and got["score"][i].tolist() == [s1, s2], \
+            (i, int(lens[i]))
+    m.close()
+    ix.close()

@@ -272,6 +272,10 @@ def test_kernel_info_follows_tiles_and_scores():
     ix = mx.Index(g.seq, 4096, 4000, 8, -8)             # bound 32000 > 31744
     assert ix.kernel_info() == (32, mx.MAXSS_KERNEL_STEP_MAX)
     ix.close()
+    # quality scores: the register banks for reads with one score pair (a
+    # two-step launch for the others)
     ix = mx.Index(g.seq, 2048, 100, 5, -4, -26, qual_scale=10)
-    assert ix.kernel_info() == (16, mx.MAXSS_KERNEL_TWO_STEP)
+    assert ix.kernel_info() == (16, mx.MAXSS_KERNEL_REGISTER_BANK)
+    ix.set_tiles(8, 0, 0)
+    assert ix.kernel_info() == (8, mx.MAXSS_KERNEL_TWO_STEP)
     ix.close()
