@@ -1197,47 +1197,92 @@ static void init_params(uint32_t seed, uint32_t kind, std::vector<float>& p) {
 // (NF - 1)), then f + 1 if f >= label)], and, when fewer than 63 negatives
 // were found, the remaining fragments other than the label in increasing id
 // order, repeated as needed.  rsel[b] = 2 * read + label strand.
-__global__ void negatives_kernel(const int32_t* __restrict__ bidx, const maxss_top2* __restrict__ labels,
-                                 const int32_t* __restrict__ hardc, uint32_t hard_k,
-                                 uint32_t hard, uint64_t key, uint64_t t, uint32_t B,
-                                 uint32_t NF, int32_t* __restrict__ cand,
-                                 int32_t* __restrict__ rsel) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// One wave per row, the row in LDS.  Each phase takes its entries in the
+// rule's order: lane l holds entry k0 + l of a chunk of 64, which is kept
+// when it is not in the row and equals no earlier entry of the chunk (an
+// earlier equal entry was either kept, or dropped because its value was
+// already in the row); the first free slots go to the kept lanes in lane
+// order.
+// Orders the wave's LDS accesses: what a lane wrote before is visible to
+// every lane after.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline bool row_has(const int32_t* row, int n, int32_t f) {
+  bool hit = false;
+  for (int j = 0; j < n; j++) hit |= row[j] == f;
+  return hit;
+}
+
+// Appends the kept candidates of a chunk (lane value f, ok = eligible),
+// at most `room`; returns how many were appended.
+__device__ inline int row_append(int32_t* row, int n, int room, int32_t f, bool ok) {
+  const uint32_t lane = threadIdx.x & 63;
+  bool dup = false;
+  for (uint32_t i = 0; i < 63; i++) {
+    const int32_t g = __shfl(f, (int)i, 64);
+    dup |= i < lane && g == f;
+  }
+  const bool keep = ok && !dup && !row_has(row, n, f);
+  const uint64_t m = __ballot(keep);
+  const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  if (keep && (int)pos < room) row[n + pos] = f;
+  const int cnt = __popcll(m);
+  return cnt < room ? cnt : room;
+}
+
+__global__ __launch_bounds__(256) void negatives_kernel(
+    const int32_t* __restrict__ bidx, const maxss_top2* __restrict__ labels,
+    const int32_t* __restrict__ hardc, uint32_t hard_k, uint32_t hard, uint64_t key, uint64_t t,
+    uint32_t B, uint32_t NF, int32_t* __restrict__ cand, int32_t* __restrict__ rsel) {
+  __shared__ int32_t rows[4][kCand];
+  const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t b = blockIdx.x * 4 + wv;
+  if (b >= B) return;  // whole waves: the rest of the block never syncs
+  int32_t* row = rows[wv];
   const int32_t r = bidx[b];
   const int32_t L = labels[r].frag[0], S2 = labels[r].frag[1];
-  int32_t* row = cand + (uint64_t)b * kCand;
-  rsel[b] = 2 * r + (labels[r].strand[0] ? 1 : 0);
-  row[0] = L;
+  if (lane == 0) {
+    rsel[b] = 2 * r + (labels[r].strand[0] ? 1 : 0);
+    row[0] = L;
+  }
   int n = 1;
-  auto seen = [&](int32_t f) {
-    for (int j = 0; j < n; j++)
-      if (row[j] == f) return true;
-    return false;
-  };
-  if (S2 >= 0 && (uint32_t)S2 < NF && S2 != L) row[n++] = S2;
+  if (S2 >= 0 && (uint32_t)S2 < NF && S2 != L) {
+    if (lane == 0) row[1] = S2;
+    n = 2;
+  }
+  wave_sync();
   if (hardc) {
-    uint32_t taken = 0;
-    for (uint32_t j = 0; j < hard_k && taken < hard && n < kCand; j++) {
-      const int32_t f = hardc[(uint64_t)b * hard_k + j];
-      if (f < 0 || f == L || seen(f)) continue;
-      row[n++] = f;
-      taken++;
-    }
+    // the model's best fragments in its order, at most `hard` of them
+    const int32_t f = lane < hard_k ? hardc[(uint64_t)b * hard_k + lane] : -1;
+    const int room = (int)hard < kCand - n ? (int)hard : kCand - n;
+    n += row_append(row, n, room, f, f >= 0 && f != L);
+    wave_sync();
   }
   if (NF > 1) {
     const uint64_t c0 = (t * B + b) * 512ull;
-    for (uint32_t k = 0; k < 512 && n < kCand; k++) {
-      int32_t f = (int32_t)(sm_unit(sm_draw(key, c0 + k)) * (double)(NF - 1));
+    for (uint32_t k0 = 0; k0 < 512 && n < kCand; k0 += 64) {
+      int32_t f = (int32_t)(sm_unit(sm_draw(key, c0 + k0 + lane)) * (double)(NF - 1));
       if (f >= L) f++;
-      if (!seen(f)) row[n++] = f;
+      n += row_append(row, n, kCand - n, f, true);
+      wave_sync();
     }
   }
-  for (uint32_t f = 0; f < NF && n < kCand; f++)
-    if ((int32_t)f != L && !seen((int32_t)f)) row[n++] = (int32_t)f;
+  for (uint32_t f0 = 0; f0 < NF && n < kCand; f0 += 64) {
+    const uint32_t f = f0 + lane;
+    n += row_append(row, n, kCand - n, (int32_t)f, f < NF && (int32_t)f != L);
+    wave_sync();
+  }
   // fewer than 64 fragments: the negatives found so far again (the label
   // itself when it is the only fragment)
-  for (int j = n; j < kCand; j++) row[j] = n > 1 ? row[1 + (j - n) % (n - 1)] : L;
+  wave_sync();
+  int32_t* out = cand + (uint64_t)b * kCand;
+  const int j = (int)lane;
+  out[j] = j < n ? row[j] : (n > 1 ? row[1 + (j - n) % (n - 1)] : L);
 }
 
 __global__ void fill_words_kernel(uint32_t* __restrict__ p, uint32_t v, uint32_t n) {
@@ -1548,7 +1593,7 @@ extern "C" maxss_status maxss_model_train(maxss_model* model, const maxss_index*
         topk_kernel<<<B, 256, 0, st>>>(Sh, NF, NF, hk, 0.0f, ones, 0, hardc, mg, fb);
         if ((s = check_hip(hipGetLastError(), "hard negatives"))) break;
       }
-      negatives_kernel<<<(B + 63) / 64, 64, 0, st>>>(bidx, labels, hk ? hardc : nullptr, hk,
+      negatives_kernel<<<(B + 3) / 4, 256, 0, st>>>(bidx, labels, hk ? hardc : nullptr, hk,
                                                       o.hard_negatives, nkey, t, B, NF, cand, m->rsel);
       if ((s = check_hip(hipGetLastError(), "negatives_kernel"))) break;
       if (o.cand_trace &&

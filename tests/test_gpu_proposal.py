@@ -343,6 +343,78 @@ def test_model_train_draws_and_trajectory(small):
     m.close()
 
 
+def test_model_train_candidate_rows_few_fragments():
+    """Candidate rows when the genome has fewer fragments than a row holds
+    (20 and 1): the uniform draws, then the fragments left in increasing id
+    order, then the negatives found repeated, exactly as the oracle's rule;
+    and rows with hard negatives: the label first, the second next, distinct
+    fragments other than the label, the hard ones among the model's own best
+    fragments."""
+    torch = _torch()
+    for G, F in ((5_000, 256), (200, 256)):
+        g = gen.uniform_genome(G, 64)
+        ix = mx.Index(g.seq, F, 100)
+        r = gen.sample_reads(g, 80, 65, [36, 51, 100], 0.0, 0.2)
+        s, o = _dev_reads(torch, r)
+        lab = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+        ix.scan(s, o, lab)
+        torch.cuda.synchronize()
+        labels = lab.cpu().numpy().view(mx.TOP2_DTYPE)
+        valid = [i for i in range(r.n) if labels["frag"][i][0] >= 0]
+        steps, B, seed = 3, 16, 5
+        m = mx.Model(seed=2, init=mx.MAXSS_INIT_GLOROT)
+        ctrace = np.zeros(steps * B * 64, np.int32)
+        m.train(ix, s, o, lab, steps, batch=B, lr=1e-3, seed=seed, val_fraction=0.0,
+                cand_trace=ctrace)
+        ctrace = ctrace.reshape(steps, B, 64)
+        for t in range(steps):
+            rows = mlp.batch_reads(seed, t, B, valid)
+            cand = np.array([mlp.batch_candidates(seed, t, B, b, int(labels["frag"][i][0]),
+                                                  int(labels["frag"][i][1]), ix.NF)
+                             for b, i in enumerate(rows)])
+            assert (ctrace[t] == cand).all(), (G, t)
+        m.close()
+        ix.close()
+    g = gen.uniform_genome(400_000, 66)
+    ix = mx.Index(g.seq, 2048, 100)
+    r = gen.sample_reads(g, 200, 67, [100], 0.0, 0.1)
+    s, o = _dev_reads(torch, r)
+    lab = torch.empty(r.n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(s, o, lab)
+    torch.cuda.synchronize()
+    labels = lab.cpu().numpy().view(mx.TOP2_DTYPE)
+    hard, B, steps = 8, 32, 4
+    m = mx.Model(seed=3, init=mx.MAXSS_INIT_PROFILE_MATCH)
+    # the model's own best fragments (lr 0 keeps the parameters), with room
+    # for float ties at the edge of its top hard + 1
+    top = torch.zeros(r.n * 24, dtype=torch.int32, device="cuda")
+    mg = torch.zeros(r.n, dtype=torch.float32, device="cuda")
+    fb = torch.zeros(r.n, dtype=torch.uint8, device="cuda")
+    m.candidates(ix, s, o, 24, 0.0, top, mg, fb)
+    ctrace = np.zeros(steps * B * 64, np.int32)
+    m.train(ix, s, o, lab, steps, batch=B, lr=0.0, seed=9, hard_negatives=hard,
+            val_fraction=0.0, cand_trace=ctrace)
+    torch.cuda.synchronize()
+    top = top.cpu().numpy().reshape(r.n, 24)
+    valid = [i for i in range(r.n) if labels["frag"][i][0] >= 0]
+    for t in range(steps):
+        rows = mlp.batch_reads(9, t, B, valid)
+        for b, i in enumerate(rows):
+            row = ctrace.reshape(steps, B, 64)[t, b]
+            L, S2 = int(labels["frag"][i][0]), int(labels["frag"][i][1])
+            assert row[0] == L and len(set(row.tolist())) == 64 and (row[1:] != L).all()
+            k = 1
+            if 0 <= S2 != L:
+                assert row[1] == S2
+                k = 2
+            # of the model's best hard + 1, at most two (label, second) are
+            # left out, so at least hard - 1 hard negatives lead the row
+            best = [f for f in top[i] if f != L and f != S2]
+            assert set(row[k:k + hard - 1].tolist()) <= set(best), (t, b)
+    m.close()
+    ix.close()
+
+
 def _cosine_candidates(ix, dreads, K):
     """Top-K fragments by the cosine of the 4-mer profiles (max over strands),
     ties to the smaller id: the non-learned ranking."""
