@@ -627,23 +627,38 @@ __global__ __launch_bounds__(256) void train_bwd_kernel(const float* __restrict_
 }
 
 // Deterministic reduction of the per-read partials into the gradient
-// (dw2, db1, db2) and of the per-read losses into the mean loss.
+// (dw2, db1, db2) and of the per-read losses into the mean loss.  A block
+// takes 64 consecutive sums (the last block the loss); thread group g of 4
+// adds the partials of reads b = g, g + 4, ... in increasing b, and the four
+// group sums are added in group order.
 __global__ __launch_bounds__(256) void train_reduce_kernel(const float* __restrict__ part,
                                                            const float* __restrict__ lossv,
                                                            uint32_t nb, float* __restrict__ grad,
                                                            float* __restrict__ loss) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. 2*kH
-  if (k < 2 * kH + 1) {
-    float s = 0.f;
-    for (uint32_t b = 0; b < nb; b++) s += part[(uint64_t)b * (2 * kH + 1) + k];
-    if (k < kH) grad[kW1 + kH + k] = s;          // dw2
-    else if (k < 2 * kH) grad[kW1 + (k - kH)] = s;  // db1
-    else grad[kParams - 1] = s;                 // db2
+  __shared__ float acc[4][64];
+  constexpr uint32_t kSums = 2 * kH + 1;
+  const uint32_t j = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const bool loss_block = blockIdx.x == (kSums + 63) / 64;
+  const uint32_t k = blockIdx.x * 64 + j;  // 0 .. 2*kH
+  float s = 0.f;
+  if (loss_block) {
+    if (j == 0)
+      for (uint32_t b = g; b < nb; b += 4) s += lossv[b];
+  } else if (k < kSums) {
+    for (uint32_t b = g; b < nb; b += 4) s += part[(uint64_t)b * kSums + k];
   }
-  if (k == 2 * kH + 1 && loss) {
-    float s = 0.f;
-    for (uint32_t b = 0; b < nb; b++) s += lossv[b];
-    *loss = s / (float)nb;
+  acc[g][j] = s;
+  __syncthreads();
+  if (g != 0) return;
+  const float t = ((acc[0][j] + acc[1][j]) + acc[2][j]) + acc[3][j];
+  if (loss_block) {
+    if (j == 0 && loss) *loss = t / (float)nb;
+  } else if (k < kH) {
+    grad[kW1 + kH + k] = t;          // dw2
+  } else if (k < 2 * kH) {
+    grad[kW1 + (k - kH)] = t;        // db1
+  } else if (k < kSums) {
+    grad[kParams - 1] = t;           // db2
   }
 }
 
@@ -1102,7 +1117,7 @@ static maxss_status train_step_impl(Model* m, const Index* ix, const uint16_t* r
       return s;
   }
   assemble_w1_kernel<<<(kW1 + 255) / 256, 256, 0, st>>>(tmp, m->grad);
-  train_reduce_kernel<<<(2 * kH + 2 + 255) / 256, 256, 0, st>>>(m->part, m->lossv, nb, m->grad, loss);
+  train_reduce_kernel<<<(2 * kH + 1 + 63) / 64 + 1, 256, 0, st>>>(m->part, m->lossv, nb, m->grad, loss);
   if ((s = check_hip(hipGetLastError(), "train reduce"))) return s;
   if (grad_out &&
       (s = check_hip(hipMemcpyAsync(grad_out, m->grad, 4ull * kParams, hipMemcpyDeviceToDevice, st),
