@@ -507,12 +507,20 @@ __device__ inline void bank_init(uint32_t la, const uint32_t (&pl)[4], const uin
       "v_mov_b64 v[224+\\j:225+\\j], %[zero]\n"
       ".endr\n"
       "s_waitcnt lgkmcnt(0)\n"
-      ".irp s, " MAXSS_IRP16 "\n" MAXSS_BANK_FILL("\\s", "\\s") ".endr\n"
-      ".irp i, 0,2,4,6,8,10,12,14\n"
+      // words 16..23 are loaded while slots 8..15 fill, words 24..31 while
+      // slots 16..23 fill
+      ".irp s, 0,1,2,3,4,5,6,7\n" MAXSS_BANK_FILL("\\s", "\\s") ".endr\n"
+      ".irp i, 0,2,4,6\n"
       "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:17+\\i offset1:18+\\i\n"
       ".endr\n"
+      ".irp s, 8,9,10,11,12,13,14,15\n" MAXSS_BANK_FILL("\\s", "\\s") ".endr\n"
+      ".irp i, 8,10,12,14\n"
+      "ds_read2_b32 v[240+\\i:241+\\i], %[la] offset0:17+\\i offset1:18+\\i\n"
+      ".endr\n"
+      "s_waitcnt lgkmcnt(4)\n"
+      ".irp s, 0,1,2,3,4,5,6,7\n" MAXSS_BANK_FILL("16+\\s", "\\s") ".endr\n"
       "s_waitcnt lgkmcnt(0)\n"
-      ".irp s, " MAXSS_IRP16 "\n" MAXSS_BANK_FILL("16+\\s", "\\s") ".endr\n"
+      ".irp s, 8,9,10,11,12,13,14,15\n" MAXSS_BANK_FILL("16+\\s", "\\s") ".endr\n"
       :
       : [la] "v"(la), [zero] "s"(0x8000800080008000ull), MAXSS_BANK_POOLS
       : "memory", MAXSS_BANK_CLOBBERS);
@@ -725,10 +733,17 @@ __device__ inline void kadane_pairs_bank(const uint32_t* __restrict__ lds, uint3
 
 #pragma clang diagnostic pop
 
+// Maximum over the wave, by DPP within the VALU (no LDS round trip): an
+// inclusive max scan (row shifts 1, 2, 4, 8, then the broadcasts of lanes 15
+// and 31 into the rows above) leaves the maximum in lane 63.
 __device__ inline int wave_max_i32(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Whether every scored position of read `rid` (length L) has the pair of
