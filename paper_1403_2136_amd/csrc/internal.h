@@ -164,6 +164,7 @@ struct NwShape {
   uint32_t cw = 0, ncols_max = 0, rowbytes = 0, grid = 0;
   uint32_t wave_cw = 0;  // columns per lane of the wave kernel, 0 = block kernel
   bool fit = false;       // fitting mode in 16 bits: the two-pass kernel (wave_cw columns per lane)
+  bool lds_moves = false; // the two-pass kernel keeps a one-strip window's moves in LDS
   size_t lds = 0;
 };
 maxss_status nw_shape(const Index* ix, uint32_t n, uint32_t pad, NwShape* sh);

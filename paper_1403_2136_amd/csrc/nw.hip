@@ -40,6 +40,7 @@ struct NwArgs {
   uint32_t rowbytes;      // bytes of move codes per DP row
   uint8_t* slab;          // [gridDim.x][m_max][rowbytes]
   uint32_t m_max;
+  uint32_t lds_moves;     // two-pass kernel: one-strip windows keep their moves in LDS
   maxss_aln* out;
   char* cigar;
   uint64_t cigar_stride;
@@ -552,6 +553,8 @@ __global__ __launch_bounds__(64) void nw_fit_kernel(NwArgs a) {
   const uint32_t ops_bytes = (a.m_max + 64u * CW + 16u + 3u) & ~3u;
   int* lb0 = (int*)(shf + mq + ops_bytes);                      // strip boundaries
   int* lb1 = lb0 + (a.m_max + 1);
+  // a one-strip window's moves, [m_max][64] bytes (row r-1, lane = byte)
+  uint8_t* lmv = a.lds_moves ? (uint8_t*)(lb1 + (a.m_max + 1)) : nullptr;
   const int lane = (int)threadIdx.x;
   uint8_t* slab = a.slab + (uint64_t)blockIdx.x * a.m_max * a.rowbytes;
   const int g = -a.gap;  // >= 0
@@ -669,6 +672,9 @@ __global__ __launch_bounds__(64) void nw_fit_kernel(NwArgs a) {
       b = lo > 0 ? (int)lo : 0;
     }
     const int W = jend - b;
+    // the window fits one strip: its moves stay in LDS, byte lane of row r-1
+    // holding columns 4 lane + 1 .. 4 lane + 4
+    const bool in_lds = lmv != nullptr && W <= kFitStrip;
     int* lb = lb0;
     int* ln = lb1;
     for (uint32_t r = lane; r <= m; r += 64) lb[r] = (int)r * a.gap;
@@ -728,8 +734,9 @@ __global__ __launch_bounds__(64) void nw_fit_kernel(NwArgs a) {
           mv |= ((L << 1) | (upw[t] & ~L)) << (2 * t);  // 0 diagonal, 1 up (I), 2 left (D)
         }
         // columns jw0, jw0+1 in bits 0..3, jw0+2, jw0+3 in bits 16..19
-        slab[(uint64_t)(r - 1) * a.rowbytes + (uint32_t)(jw0 - 1) / 4u] =
-            (uint8_t)((mv & 0xFu) | ((mv >> 12) & 0xF0u));
+        const uint8_t mb = (uint8_t)((mv & 0xFu) | ((mv >> 12) & 0xF0u));
+        if (in_lds) lmv[(r - 1) * 64u + (uint32_t)lane] = mb;
+        else slab[(uint64_t)(r - 1) * a.rowbytes + (uint32_t)(jw0 - 1) / 4u] = mb;
         if (lane == 63) ln[r] = hi16(Db[HB - 1]);  // the strip's last column
       }
       __syncthreads();  // ln complete; lb no longer read
@@ -746,7 +753,8 @@ __global__ __launch_bounds__(64) void nw_fit_kernel(NwArgs a) {
         if (jj == 0) mv = 1;
         else {
           const uint32_t t = (uint32_t)(jj - 1);
-          const uint8_t byte = slab[(uint64_t)(ii - 1) * a.rowbytes + (t >> 2)];
+          const uint8_t byte = in_lds ? lmv[(uint32_t)(ii - 1) * 64u + (t >> 2)]
+                                      : slab[(uint64_t)(ii - 1) * a.rowbytes + (t >> 2)];
           mv = (byte >> (2 * (t & 3))) & 3u;
         }
         if (mv == 0) {
@@ -861,10 +869,22 @@ maxss_status nw_shape(const Index* ix, uint32_t n, uint32_t pad, NwShape* sh) {
     sh->ncols_max = 64 * sh->wave_cw;
     sh->rowbytes = sh->ncols_max / 4;
     sh->lds = ((m_max + 15u) & ~15u) + m_max + sh->ncols_max + 16;
-    if (sh->fit)
+    const void* fn = sh->fit ? fit_kernel_for((int)sh->wave_cw) : wave_kernel_for((int)sh->wave_cw);
+    sh->lds_moves = false;
+    if (sh->fit) {
       sh->lds = ((m_max + 15u) & ~15u) + ((m_max + sh->ncols_max + 16u + 3u) & ~3u) +
                 2 * ((size_t)m_max + 1) * 4;
-    const void* fn = sh->fit ? fit_kernel_for((int)sh->wave_cw) : wave_kernel_for((int)sh->wave_cw);
+      // room for a one-strip window's moves when it costs no resident waves
+      const size_t with = sh->lds + 64 * (size_t)m_max;
+      int occ0 = 0, occ1 = 0;
+      if (with <= 65536 &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ0, fn, 64, sh->lds) == hipSuccess &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, fn, 64, with) == hipSuccess &&
+          occ1 >= occ0 && occ1 > 0) {
+        sh->lds = with;
+        sh->lds_moves = true;
+      }
+    }
     if (sh->lds > 160 * 1024)
       return fail(MAXSS_EINVAL, "NW region too wide for LDS (%zu bytes)", sh->lds);
     maxss_status s;
@@ -922,6 +942,7 @@ maxss_status nw_pipeline(const Index* ix, const EncodedReads& er, uint32_t n,
   a.gap = qual_mode(ix) ? ix->p.gap * (int)ix->p.qual_scale : ix->p.gap;
   a.global_mode = (ix->p.flags & MAXSS_NW_GLOBAL) ? 1 : 0;
   a.cw = sh.cw; a.rowbytes = sh.rowbytes; a.slab = slab; a.m_max = ix->p.max_read_len;
+  a.lds_moves = sh.lds_moves ? 1u : 0u;
   a.out = dout; a.cigar = dcig; a.cigar_stride = cigar_stride;
   const uint32_t grid = sh.grid < n ? sh.grid : n;
   if (sh.fit) {
