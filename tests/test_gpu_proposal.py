@@ -415,6 +415,62 @@ def test_model_train_candidate_rows_few_fragments():
     ix.close()
 
 
+def test_proposed_path_full_size_sampled():
+    """The proposed path in the bench's configuration on the full bacterial
+    workload (100,000 reads of 100 bp, 2,269 fragments, K = 64, the exact-score
+    guard at the bench's min_score 20 and a margin threshold at the 70th
+    percentile of the margins), one call; 40 sampled reads are checked against
+    the oracle: the keep or fall-back decision from the oracle's exact values,
+    a kept read's top-2 among its candidates (with the full scan's
+    representatives for the fragments both report), a fallen-back read's
+    full-scan record."""
+    torch = _torch()
+    w = gen.workload("bacterial")
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap)
+    m = mx.Model(seed=0, init=mx.MAXSS_INIT_PROFILE_MATCH)
+    K, n, min_score = 64, w.reads.n, 20
+    s, o = _dev_reads(torch, w.reads)
+    cand = torch.zeros(n * K, dtype=torch.int32, device="cuda")
+    mg = torch.zeros(n, dtype=torch.float32, device="cuda")
+    fb0 = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    m.candidates(ix, s, o, K, 0.0, cand, mg, fb0)
+    torch.cuda.synchronize()
+    mg_h = mg.cpu().numpy()
+    tau = float(np.quantile(mg_h, 0.7))
+    out = torch.zeros(n * 32, dtype=torch.uint8, device="cuda")
+    fb = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    m.scan(ix, s, o, K, tau, out, fb, min_score=min_score)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    fb = fb.cpu().numpy()
+    cand = cand.cpu().numpy().reshape(n, K)
+    m.close()
+    ix.close()
+    idx = np.unique(gen.Stream(78, "proposal.sample").integers(0, n, 40))
+    sub = w.reads.subset(idx)
+    full, vals = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, nthreads=16,
+                             want_values=True)
+    kept = 0
+    for j, i in enumerate(idx):
+        c = [int(f) for f in cand[i] if f >= 0]
+        assert len(c) == K
+        keep = max(int(vals[j][f]) for f in c) >= min_score or mg_h[i] >= tau
+        assert bool(fb[i]) == (not keep), i
+        if not keep:
+            for f in ("frag", "score", "offset", "strand"):
+                assert (got[f][i] == full[f][j]).all(), (i, f)
+            continue
+        kept += 1
+        f1, s1, f2, s2 = mlp.top2_among(vals[j], c)
+        assert got["frag"][i].tolist() == [f1, f2] and got["score"][i].tolist() == [s1, s2], i
+        for e in (0, 1):
+            for k in (0, 1):
+                if got["frag"][i][e] == full["frag"][j][k]:
+                    assert got["offset"][i][e] == full["offset"][j][k], (i, e, k)
+                    assert got["strand"][i][e] == full["strand"][j][k], (i, e, k)
+    assert 0 < kept < idx.size
+
+
 def _cosine_candidates(ix, dreads, K):
     """Top-K fragments by the cosine of the 4-mer profiles (max over strands),
     ties to the smaller id: the non-learned ranking."""
