@@ -122,3 +122,26 @@ def test_fast_candidate_scan_exact_on_candidates():
         assert got["frag"][i].tolist() == [f1, f2] and got["score"][i].tolist() == [s1, s2], i
     m.close()
     ix.close()
+
+
+def test_fast_full_size_sampled():
+    """The bench's fast leg at full size: the 100,000 bacterial reads with
+    MAXSS_FAST in one call; 40 sampled reads against the oracle's fast scan."""
+    import torch
+    assert torch.cuda.is_available()
+    w = gen.workload("bacterial")
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap, flags=mx.MAXSS_FAST)
+    s = torch.from_numpy(np.array(w.reads.seq)).cuda()
+    o = torch.from_numpy(w.reads.offsets.astype(np.int64)).cuda()
+    out = torch.zeros(w.reads.n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(s, o, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    ix.close()
+    idx = np.unique(gen.Stream(80, "fast.sample").integers(0, w.reads.n, 40))
+    sub = w.reads.subset(idx)
+    ref = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, flags=oracle.FAST,
+                      nthreads=16)
+    for f in ("frag", "score", "offset", "strand"):
+        bad = np.nonzero((got[idx][f] != ref[f]).any(axis=1))[0]
+        assert bad.size == 0, (f, idx[bad[:3]])

@@ -339,3 +339,41 @@ def test_quality_split_candidate_scan():
             (i, int(lens[i]))
     m.close()
     ix.close()
+
+
+def test_quality_full_size_sampled():
+    """The bench's quality leg at full size: the 100,000 bacterial reads with
+    their synthetic qualities at qual_scale 10 (98% of them on the
+    register-bank launch of the split), device reads in one call; 40 sampled
+    reads against the oracle, including every sampled read whose bases carry
+    more than one score pair."""
+    torch = _torch()
+    w = gen.workload("bacterial")
+    q = gen.sample_qualities(w.reads, 91)
+    ix = mx.Index(w.genome.seq, w.F, w.max_read_len, w.M, w.X, w.gap, qual_scale=10)
+    s = torch.from_numpy(np.array(w.reads.seq)).cuda()
+    o = torch.from_numpy(w.reads.offsets.astype(np.int64)).cuda()
+    out = torch.zeros(w.reads.n * 32, dtype=torch.uint8, device="cuda")
+    ix.scan(s, o, out, qual=torch.from_numpy(q).cuda())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(mx.TOP2_DTYPE)
+    ix.close()
+    # the sample: 30 drawn reads plus 10 reads whose bases carry more than one
+    # (match, mismatch) pair (the score table's rule, halves rounded away
+    # from zero; Phred >= 14 gives (10, -3))
+    x = 1.0 - 10.0 ** (-(q.astype(np.float64) - 33) / 10.0)
+    rnd = lambda v: np.sign(v) * np.floor(np.abs(v) + 0.5)
+    pair = rnd(w.M * x * 10) * 256 + rnd(w.X * x * 10 / 3.0)
+    starts = w.reads.offsets[:-1].astype(np.int64)
+    first = np.repeat(pair[starts], w.reads.lengths().astype(np.int64))
+    mixed = np.nonzero(np.add.reduceat((pair != first).astype(np.int64), starts) > 0)[0]
+    assert mixed.size > 100
+    st = gen.Stream(79, "qual.sample")
+    idx = np.unique(np.concatenate([st.integers(0, w.reads.n, 30),
+                                    mixed[st.integers(0, mixed.size, 10)]]))
+    sub = w.reads.subset(idx)
+    qs = np.concatenate([q[int(w.reads.offsets[i]):int(w.reads.offsets[i + 1])] for i in idx])
+    ref = oracle.scan(w.genome.seq, w.F, sub.seq, sub.offsets, w.M, w.X, nthreads=16, quals=qs,
+                      qscale=10)
+    assert_same(got[idx], ref, "bacterial quality sample")
+    assert (got["frag"][:, 0] != got["frag"][:, 1]).all()
